@@ -1,0 +1,235 @@
+"""Pins for the CPU checker's estimator (paper section 2.3 and eq. 10) against
+what the mathematics fixes, at any time step:
+
+* harmonic data and no source: E[u_p] = h(x0) exactly under the overshoot
+  exit rule (the Gaussian mean-value property makes h(X_n) a martingale);
+* constant density with quadratic data Phi = (2/3) pi G rho0 |x|^2 + h:
+  E[u_p] = Phi(x0) exactly, because |X_n|^2 - 3 n dt is a martingale.  This
+  pins the step scale sqrt(dt), the trapezoid weight, the 2 pi G factor and
+  the sign of the source term;
+* the uniform ball and the SI prism against their closed forms;
+* g_z by common-random-number central differences against the difference of
+  the closed form;
+* mean step counts against the exact expected exit time of a box;
+* occupation counts (the adjoint) against the linearity of u in rho.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+from paper_1709_07469_amd import workloads as W
+
+BOX = dict(box_lo=np.array([-1.0, -1.0, -1.0]), box_hi=np.array([1.0, 1.0, 1.0]))
+ST4 = np.array([[0.0, 0.0, 0.0], [0.5, -0.3, 0.2], [-0.7, 0.6, -0.4], [0.1, 0.85, 0.7]])
+
+
+def _harmonic_quadratic():
+    # h = 0.4 + x - 0.5 y + 0.25 z + 0.3 (x^2 - y^2) + 0.6 xz - 0.2 yz + 0.1 (z^2 - x^2)
+    # as (c0, b, A00, A01, A02, A11, A12, A22) with trace(A) = 0
+    return np.array([0.4, 1.0, -0.5, 0.25, 0.3 - 0.1, 0.0, 0.3, -0.3, -0.1, 0.1])
+
+
+def _quad_value(q, x):
+    A = np.array([[q[4], q[5], q[6]], [q[5], q[7], q[8]], [q[6], q[8], q[9]]])
+    return q[0] + q[1:4] @ x + x @ A @ x
+
+
+def _zscores(stats, targets):
+    return np.array([(s["mean"] - t) / s["se"] for s, t in zip(stats, targets)])
+
+
+@pytest.mark.parametrize("stream", [oracle.STREAM_F64, oracle.STREAM_F32])
+def test_harmonic_data_is_reproduced(stream):
+    q = _harmonic_quadratic()
+    pr = W.Problem(stations=ST4, dt=1e-2, paths_per_station=20000, seed=11, G=1.0,
+                   bc_kind=W.BC_QUADRATIC, bc_data=q, **BOX)
+    stats, u, st = oracle.solve(pr, 0, stream=stream)
+    z = _zscores(stats, [_quad_value(q, x) for x in ST4])
+    assert np.all(np.abs(z) < 4.0), z
+
+
+@pytest.mark.parametrize("grid", [False, True])
+def test_constant_density_quadratic_data_is_exact(grid):
+    G, rho0 = 0.7, 1.5
+    k = 2.0 / 3.0 * math.pi * G * rho0
+    q = _harmonic_quadratic().copy()
+    q[4] += k
+    q[7] += k
+    q[9] += k
+    # a coarse step: the invariant is exact at any dt, and one step's source
+    # term is then large against the standard error
+    kw = dict(stations=ST4, dt=4e-2, paths_per_station=20000, seed=3, G=G, bc_kind=W.BC_QUADRATIC, bc_data=q, **BOX)
+    if grid:
+        # constant voxel grid reaching well past the box (exit points overshoot)
+        n = 16
+        kw.update(rho=np.full((n, n, n), rho0, dtype=np.float32), grid_origin=np.full(3, -3.0),
+                  grid_spacing=np.full(3, 6.0 / n))
+    else:
+        kw.update(prisms=np.array([[-10, -10, -10, 10, 10, 10, rho0]], dtype=float))
+    pr = W.Problem(**kw)
+    stats, u, st = oracle.solve(pr, 0)
+    z = _zscores(stats, [_quad_value(q, x) for x in ST4])
+    assert np.all(np.abs(z) < 4.0), z
+    # the source term is a large part of u here: dropping the exiting step or
+    # using the paper's sqrt(2 dt) step would move it by many standard errors
+    src = 2.0 * math.pi * G * rho0 * pr.dt
+    for s in stats:
+        assert src / s["se"] > 8.0
+
+
+def test_uniform_ball_cfg1_against_closed_form():
+    pr = W.cfg1(10_000)
+    stats, u, st = oracle.solve(pr, 0)
+    targets = [oracle.exact_potential(pr, x) for x in pr.stations]
+    z = _zscores(stats, targets)
+    assert np.all(np.abs(z) < 4.0), z
+    assert np.all(np.array([s["n_trunc"] for s in stats]) == 0)
+    # relative standard error ~ 1.1-1.4 / sqrt(N) per station
+    rel = np.array([s["se"] / abs(t) for s, t in zip(stats, targets)])
+    assert np.all((rel > 0.5e-2) & (rel < 2.5e-2))
+
+
+def test_uniform_ball_gz_crn_against_closed_form_difference():
+    pr = W.cfg1(10_000)
+    h = math.sqrt(pr.dt)
+    stats, d, st = oracle.solve(pr, 1)
+    M = pr.bc_data[3]
+    z = np.array([x[2] for x in pr.stations])
+    fd_exact = M / (z * z - h * h)          # central difference of -M/|z| at step h
+    zz = _zscores(stats, fd_exact)
+    assert np.all(np.abs(zz) < 4.0), zz
+    # the common-random-number pair is far less noisy than independent walks
+    stats_ind, _, _ = oracle.solve(pr.replace(pairing=W.PAIR_INDEPENDENT, paths_per_station=2000), 1)
+    assert np.all(np.array([s["se"] for s in stats_ind]) > 2.0 * np.array([s["se"] for s in stats]))
+
+
+def test_si_prism_cfg2_subset_against_closed_form():
+    pr = W.cfg2(2000)
+    pr = pr.replace(stations=pr.stations[[0, 27, 36, 63]])
+    stats, u, st = oracle.solve(pr, 0)
+    targets = [oracle.exact_potential(pr, x) for x in pr.stations]
+    z = _zscores(stats, targets)
+    assert np.all(np.abs(z) < 4.0), z
+
+
+def _box_exit_time(x, lo, hi, kmax=201):
+    """E[tau] of standard BM from x in the box: the survival function is the
+    product over axes of the interval survival series
+    S(t) = sum_{k odd} 4/(k pi) sin(k pi (x - a)/L) exp(-k^2 pi^2 t / (2 L^2))."""
+    def surv(t):
+        tot = 1.0
+        for c in range(3):
+            L = hi[c] - lo[c]
+            k = np.arange(1, kmax, 2)
+            tot *= np.sum(4.0 / (k * np.pi) * np.sin(k * np.pi * (x[c] - lo[c]) / L)
+                          * np.exp(-k * k * np.pi ** 2 * t / (2 * L * L)))
+        return tot
+    val, _ = integrate.quad(surv, 1e-12, 50.0, limit=400)
+    return val
+
+
+def test_mean_steps_match_expected_exit_time():
+    dt = 1e-4
+    pr = W.Problem(stations=ST4[:2], dt=dt, paths_per_station=6000, seed=5, bc_kind=W.BC_ZERO, **BOX)
+    stats, u, st = oracle.solve(pr, 0)
+    for s, x in zip(stats, ST4[:2]):
+        et = _box_exit_time(x, BOX["box_lo"], BOX["box_hi"])
+        steps = (st[0] if x is ST4[0] else st[1]).astype(float)
+        se = np.std(steps) / np.sqrt(len(steps))
+        # the discretely monitored walk exits a little later than the
+        # continuous one (by O(sqrt(dt)), ~2% here)
+        assert et / dt - 4 * se < s["mean_steps"] < et / dt * 1.04 + 4 * se, (s["mean_steps"], et / dt)
+
+
+def test_station_stats_match_two_pass_fsum():
+    rng = np.random.Generator(np.random.PCG64(0))
+    u = rng.normal(3.0, 2.0, size=5001) * 1e-7 + 1e5
+    steps = rng.integers(1, 1000, size=5001).astype(np.uint32)
+    steps[[3, 100, 4000]] |= np.uint32(oracle.TRUNC_FLAG)
+    keep = (steps & np.uint32(oracle.TRUNC_FLAG)) == 0
+    s = oracle.station_stats(u, steps)
+    mean = math.fsum(u[keep]) / keep.sum()
+    var = math.fsum((u[keep] - mean) ** 2) / (keep.sum() - 1)
+    assert s["n"] == keep.sum() and s["n_trunc"] == 3
+    # plain summation in path order: error bound n * eps relative
+    assert s["mean"] == pytest.approx(mean, rel=len(u) * 2.3e-16)
+    assert s["var"] == pytest.approx(var, rel=1e-9)
+    assert s["se"] == pytest.approx(math.sqrt(var / keep.sum()), rel=1e-9)
+    assert s["max_steps"] == int((steps & np.uint32(0x7FFFFFFF)).max())
+
+
+def test_standard_error_scales_as_inverse_sqrt_n():
+    pr = W.cfg1(16000).replace(stations=W.cfg1().stations[[2]])
+    s16 = oracle.solve(pr, 0)[0][0]["se"]
+    s4 = oracle.solve(pr, 0, n_paths=4000)[0][0]["se"]
+    assert s4 / s16 == pytest.approx(2.0, rel=0.12)
+
+
+def test_path_offset_resumes_the_same_streams():
+    pr = W.cfg1(1000).replace(stations=W.cfg1().stations[:2])
+    _, u_all, st_all = oracle.solve(pr, 0)
+    _, u_hi, st_hi = oracle.solve(pr.replace(path_offset=600), 0, n_paths=400)
+    assert np.array_equal(u_all[:, 600:], u_hi) and np.array_equal(st_all[:, 600:], st_hi)
+
+
+def test_truncation_is_counted_and_excluded():
+    pr = W.cfg1(400).replace(max_steps=200, stations=W.cfg1().stations[:2])
+    stats, u, st = oracle.solve(pr, 0)
+    tr = (st & np.uint32(oracle.TRUNC_FLAG)) != 0
+    assert tr.any() and (~tr).any()
+    assert np.all(np.isnan(u[tr])) and np.all(np.isfinite(u[~tr]))
+    assert np.all((st[tr] & np.uint32(0x7FFFFFFF)) == 200)
+    assert np.all((st[~tr] & np.uint32(0x7FFFFFFF)) <= 200)
+    for s in range(2):
+        assert stats[s]["n_trunc"] == tr[s].sum()
+        assert stats[s]["mean"] == pytest.approx(np.mean(u[s][~tr[s]]), rel=1e-13)
+
+
+def test_intersect_exit_points_lie_on_the_boundary_and_bias_shrinks():
+    q = np.array([0.0, 0.0, 0.0, 1.0, 0, 0, 0, 0, 0, 0])          # h = z
+    st = np.array([[0.0, 0.0, 0.8]])
+    items = np.stack([np.zeros(3000, dtype=np.int64), np.arange(3000)], axis=1)
+    pr = W.Problem(stations=st, dt=4e-2, paths_per_station=3000, seed=1, bc_kind=W.BC_QUADRATIC, bc_data=q,
+                   exit_rule=W.EXIT_INTERSECT, **BOX)
+    u, steps, _, xe = oracle.run_paths(pr, 0, items, want_exit=True)
+    on_face = np.isclose(np.abs(xe), 1.0, rtol=0, atol=0).sum(axis=1)
+    assert np.all(on_face >= 1) and np.all(np.abs(xe) <= 1.0 + 1e-15)
+    biases = []
+    for dt in (4e-2, 2.5e-3):
+        stats, _, _ = oracle.solve(pr.replace(dt=dt, paths_per_station=20000), 0)
+        biases.append((stats[0]["mean"] - 0.8, stats[0]["se"]))
+    (b0, s0), (b1, s1) = biases
+    assert b0 < -4 * s0                      # the intersected point under-reads z
+    assert abs(b1) < 0.5 * abs(b0)          # O(sqrt(dt)): a quarter step ~ half the bias
+
+
+def test_occupation_counts_are_the_derivative_of_u():
+    pr = W.cfg5(200)
+    pr = pr.replace(stations=pr.stations[:3])
+    G, dt = pr.G, pr.dt
+    w = 2.0 * math.pi * G * (0.5 * dt)
+    cp, _ = oracle.occupation(pr, 0, 0, 200)
+    stats, u, st = oracle.solve(pr, 0)
+    rho = pr.rho.ravel().astype(np.float64)
+    # zero boundary data: u_p = -w S_p and S is linear in rho
+    for s in range(3):
+        total = -w * float(cp[s].astype(np.float64) @ rho)
+        assert math.fsum(u[s]) == pytest.approx(total, rel=1e-12)
+    # a finite difference in one voxel (same streams) changes sum u by -w eps c_v
+    v = int(np.argmax(cp[0]))
+    eps = 3.0
+    rho2 = pr.rho.copy().ravel()
+    rho2[v] += eps
+    _, u2, _ = oracle.solve(pr.replace(rho=rho2.reshape(pr.rho.shape)), 0)
+    for s in range(3):
+        assert math.fsum(u2[s]) - math.fsum(u[s]) == pytest.approx(-w * eps * float(cp[s, v]), rel=1e-9)
+    # g_z counts: the pair difference
+    cp1, cm1 = oracle.occupation(pr, 1, 0, 200)
+    stats1, d, _ = oracle.solve(pr, 1)
+    h = math.sqrt(dt)
+    for s in range(3):
+        total = -w * float((cp1[s].astype(np.float64) - cm1[s].astype(np.float64)) @ rho) / (2 * h)
+        assert math.fsum(d[s]) == pytest.approx(total, rel=1e-10)

@@ -1,0 +1,103 @@
+"""Pins for the CPU checker's random streams (Philox4x32-10 and the
+Box-Muller maps), independent of the checker's own code:
+
+* Philox words against rocRAND's header-only host engine, an independent
+  implementation of the same published generator (Salmon et al., SC'11),
+  compiled and run here on the CPU;
+* the normal streams against N(0,1): moments and a Kolmogorov-Smirnov test
+  with scipy, and independence across path, station and problem counters.
+"""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def rocrand_tool(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("hipcc / rocRAND headers not available")
+    exe = str(tmp_path_factory.mktemp("rr") / "rocrand_philox")
+    subprocess.check_call([hipcc, "-O1", "--offload-arch=gfx950", os.path.join(HERE, "rocrand_philox_ref.cpp"),
+                           "-o", exe], stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    return exe
+
+
+def test_philox_matches_rocrand(rocrand_tool):
+    rng = np.random.Generator(np.random.PCG64(123))
+    rows = [[0, 0, 0, 0, 0, 0], [0xFFFFFFFF] * 6, [1, 2, 3, 4, 5, 6]]
+    rows += rng.integers(0, 2 ** 32, size=(200, 6), dtype=np.uint64).tolist()
+    # counters of the form used by the solver: (block k, path p, station s, problem m)
+    rows += [[k, p, s, m, 0, 0] for k in (0, 1, 7) for p in (0, 99999) for s in (0, 63) for m in (0, 31)]
+    text = "\n".join(" ".join("%x" % v for v in r) for r in rows) + "\n"
+    out = subprocess.run([rocrand_tool], input=text, capture_output=True, text=True, check=True).stdout
+    ref = [[int(w, 16) for w in line.split()] for line in out.strip().splitlines()]
+    assert len(ref) == len(rows)
+    for r, e in zip(rows, ref):
+        got = oracle.philox4x32_10(r[:4], r[4:]).tolist()
+        assert got == e, (r, got, e)
+
+
+def _normals(stream, n_paths, n_per, seed=0, m=0, s=0):
+    return np.array([[oracle.normal(stream, seed, m, s, p, j) for j in range(n_per)] for p in range(n_paths)])
+
+
+@pytest.mark.parametrize("stream", [oracle.STREAM_F64, oracle.STREAM_F32])
+def test_normal_stream_moments_and_ks(stream):
+    z = _normals(stream, 4000, 12).ravel()          # 48000 variates
+    n = z.size
+    se = 1.0 / np.sqrt(n)
+    assert abs(z.mean()) < 4 * se
+    assert abs(z.var() - 1.0) < 4 * np.sqrt(2.0 / n)
+    assert abs(np.mean(z ** 4) - 3.0) < 4 * np.sqrt(96.0 / n)
+    assert abs(np.mean(z ** 3)) < 4 * np.sqrt(15.0 / n)
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+
+
+@pytest.mark.parametrize("stream", [oracle.STREAM_F64, oracle.STREAM_F32])
+def test_streams_independent_across_counters(stream):
+    # the same index j in different paths, stations and problems must be
+    # uncorrelated: correlation of paired variates ~ N(0, 1/n)
+    n = 6000
+    a = np.array([oracle.normal(stream, 7, 0, 0, p, 5) for p in range(n)])
+    b = np.array([oracle.normal(stream, 7, 0, 1, p, 5) for p in range(n)])
+    c = np.array([oracle.normal(stream, 7, 1, 0, p, 5) for p in range(n)])
+    d = np.array([oracle.normal(stream, 8, 0, 0, p, 5) for p in range(n)])
+    for x, y in ((a, b), (a, c), (a, d), (b, c)):
+        assert abs(np.corrcoef(x, y)[0, 1]) < 4.5 / np.sqrt(n)
+    # consecutive variates within one path are uncorrelated too (x, y, z of a step)
+    w = _normals(stream, 3000, 6)
+    for j in range(5):
+        assert abs(np.corrcoef(w[:, j], w[:, j + 1])[0, 1]) < 4.5 / np.sqrt(3000)
+
+
+def test_f64_stream_uses_53_bit_uniforms():
+    # the FP64 stream must resolve the normal tail beyond the 24-bit limit
+    # sqrt(-2 ln 2^-24) = 5.77; with 2e5 FP64 variates values beyond 4.5
+    # appear with probability ~ 1.4 (expected count), FP32 caps at 5.77
+    z = _normals(oracle.STREAM_F32, 20000, 8).ravel()
+    assert np.abs(z).max() <= np.sqrt(-2.0 * np.log(2.0 ** -24)) + 1e-12
+
+
+def test_stream_block_layout_matches_philox_words():
+    # block k of path (m, s, p) is Philox((k, p, s, m), (seed lo, seed hi));
+    # the FP32 stream's first normal is the Box-Muller cosine branch of the
+    # first two 24-bit uniforms of that block
+    seed = (5 << 32) | 9
+    w = oracle.philox4x32_10([3, 11, 2, 1], [9, 5]).astype(np.uint64)
+    u0 = ((w[0] >> 8) + 1) * 2.0 ** -24
+    u1 = ((w[1] >> 8) + 1) * 2.0 ** -24
+    z12 = oracle.normal(oracle.STREAM_F32, seed, 1, 2, 11, 12)   # j = 12 -> block 3, slot 0
+    assert z12 == pytest.approx(np.sqrt(-2 * np.log(u0)) * np.cos(2 * np.pi * u1), rel=1e-14, abs=1e-14)
+    a = (((int(w[1]) << 21) | (int(w[0]) >> 11)) + 1) * 2.0 ** -53
+    b = (((int(w[3]) << 21) | (int(w[2]) >> 11)) + 1) * 2.0 ** -53
+    z7 = oracle.normal(oracle.STREAM_F64, seed, 1, 2, 11, 7)     # j = 7 -> block 3, slot 1
+    assert z7 == pytest.approx(np.sqrt(-2 * np.log(a)) * np.sin(2 * np.pi * b), rel=1e-14, abs=1e-14)
