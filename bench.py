@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the Monte Carlo Feynman-Kac gravity solver on one MI355X.
+
+One step is one pass of the hot path over the benchmark problem: the
+potential u and the vertical acceleration g_z (common-random-number central
+difference) at all 64 stations of the SI-prism workload -- box
+[0,1000]^2 x [-500,100] m, one prism [400,600]x[450,550]x[-300,-150] m of
+300 kg/m^3, exact prism data on the faces, 1e5 walks per station,
+sqrt(dt) = 2 m, FP64.  Inputs live in device memory before timing starts.
+
+Prints one JSON line: Brownian steps per second of the whole job (exact
+in-kernel step counts over the event-timed region), the ALU roofline of the
+walk kernel, station estimates per second at fixed relative standard error,
+the mixed-precision kernel on the same workload, and the CPU oracle timed on
+a bounded sample on the host.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64|mixed]
+                  [--no-cpu-baseline] [--cpu-seconds S]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Brownian steps/s and station estimates/s at fixed std error; % FP32/FP64 VALU peak"
+
+# Peak full-rate VALU issue of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# lane-operations per second (the same count that gives 78.6 TFLOP/s of FP64
+# FMA at 2 FLOP per lane-op).
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def algorithmic_ops_per_step(precision: str) -> float:
+    """Full-rate VALU lane-operation slots one Euler-Maruyama step of the
+    benchmark problem needs (one analytic prism, overshoot exit), counted
+    from the method's arithmetic with gfx950 issue costs (derivation in
+    DESIGN.md, table "Algorithmic work per step").
+
+    Philox4x32-10 block: 10 rounds x (2 v_mad_u64_u32 at 4 slots + 2 v_xor3
+    at 1 slot) = 100 slots.  FP64 stream: 1.5 blocks, 3 normals from 1.5
+    Box-Muller pairs, each pair needing one log, one sqrt, one sin and one
+    cos (counted as one transcendental-unit operation each, 4 slots) plus 2
+    multiplies, and 2 uniforms x 4 integer/convert ops.  Step: 3 FMA,
+    prism membership 6 compares + 1 add, trapezoid 2 adds, exit test 6
+    compares.  Mixed stream: 0.75 blocks, 4 uniforms per block x 3 ops,
+    the transcendentals on the hardware unit."""
+    philox = 10 * (2 * 4 + 2 * 1)
+    step_common = 3 + 7 + 2 + 6
+    if precision == "f64":
+        blocks = 1.5
+        uniforms = blocks * 2 * 4
+        bm = 1.5 * (4 * 4 + 2)
+        return blocks * philox + uniforms + bm + step_common
+    blocks = 0.75
+    uniforms = blocks * 4 * 3
+    bm = 1.5 * (4 * 4 + 2)
+    return blocks * philox + uniforms + bm + step_common + 2   # +2: f32->f64 converts of the sum
+
+
+def station_estimates_per_s(stats, steps_per_s, rel_se):
+    """Stations per second at a target relative standard error: station s
+    needs N_s = var_s / (rel_se |mean_s|)^2 samples of mean_steps_s steps."""
+    work = 0.0
+    for s in stats:
+        if not (s["n"] > 1 and s["mean"] != 0):
+            continue
+        n_req = s["var"] / (rel_se * abs(s["mean"])) ** 2
+        work += n_req * s["mean_steps"]
+    return len(stats) / (work / steps_per_s) if work > 0 else None
+
+
+def cpu_baseline(prob, seconds):
+    """The oracle on the host cores: the first n walks of every station, u
+    and g_z, n grown until about `seconds` of work."""
+    import numpy as np
+
+    import oracle
+    S = prob.n_stations
+    n, elapsed, steps = 2, 0.0, 0
+    while True:
+        t0 = time.perf_counter()
+        tot = 0
+        for kind in (0, 1):
+            items = np.stack([np.repeat(np.arange(S), n), np.tile(np.arange(n), S)], axis=1)
+            _, st = oracle.run_paths(prob, kind, items)
+            tot += int((st & np.uint32(0x7FFFFFFF)).astype(np.int64).sum())
+        elapsed = time.perf_counter() - t0
+        steps = tot
+        if elapsed >= 0.6 * seconds or n >= prob.paths_per_station:
+            break
+        n = min(prob.paths_per_station, max(n + 1, int(n * min(8.0, 1.1 * seconds / max(elapsed, 1e-3)))))
+    return {"value": steps / elapsed, "unit": "Brownian steps/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"all {S} stations x first {n} walks, u and g_z (FP64): {steps} steps in {elapsed:.1f} s"}
+
+
+def run(precision_name, K, Wm, cpu_seconds, want_cpu):
+    import numpy as np
+    import torch
+
+    from paper_1709_07469_amd import fkgrav as F
+    from paper_1709_07469_amd import workloads as W
+
+    prec = W.PREC_F64 if precision_name == "f64" else W.PREC_MIXED_F64ACC
+    prob = W.cfg2(precision=prec)
+    S = prob.n_stations
+    P = F.Prepared(prob)
+    ws_u = F.alloc_workspace(F.fk_workspace_bytes(0, S, P.params))
+    ws_g = F.alloc_workspace(F.fk_workspace_bytes(1, S, P.params))
+    out_u, out_g = F.alloc_stats(S), F.alloc_stats(S)
+
+    def step(params):
+        F.fk_solve_potential(P.stations, P.box, P.source, P.bc, params, out_u, ws_u)
+        F.fk_solve_gz(P.stations, P.box, P.source, P.bc, params, out_g, ws_g)
+
+    for _ in range(Wm):
+        step(P.params)
+    torch.cuda.synchronize()
+    F.fk_timing_read()
+    F.fk_timing_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(K):
+        step(P.params)
+    e1.record()
+    torch.cuda.synchronize()
+    F.fk_timing_enable(False)
+    walk_ms = F.fk_timing_read()
+    elapsed = e0.elapsed_time(e1) / 1e3
+    su, sg = F.stats_to_numpy(out_u)[:S], F.stats_to_numpy(out_g)[:S]
+    steps_per_pass = int(su["sum_steps"].sum()) + int(sg["sum_steps"].sum())
+    value = steps_per_pass * K / elapsed
+
+    ops = algorithmic_ops_per_step(precision_name)
+    achieved = steps_per_pass * K * ops / (sum(walk_ms) * 1e-3) / 1e12
+    peak = PEAK_LANE_OPS / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tops/s", "frac": achieved / peak,
+            "traffic": None, "kernel": "walk_f64_kernel" if precision_name == "f64" else "walk_f32_kernel<false>",
+            "ops_per_step": ops, "kernel_avg_ms": float(np.mean(walk_ms)), "launches": len(walk_ms),
+            "kernel_share_of_step": sum(walk_ms) / (elapsed * 1e3)}
+
+    rows_u = [dict(zip(su.dtype.names, r)) for r in su.tolist()]
+    rows_g = [dict(zip(sg.dtype.names, r)) for r in sg.tolist()]
+    est = {"u_rel_se_1e-3": station_estimates_per_s(rows_u, value, 1e-3),
+           "gz_rel_se_1e-2": station_estimates_per_s(rows_g, value, 1e-2)}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "Brownian steps/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision_name == "f64" else "f32-step/f64-acc", "data": "synthetic",
+        "config": {"workload": "SI prism 300 kg/m^3 in box [0,1000]^2x[-500,100] m, 8x8 stations at z=0, "
+                               "1e5 walks/station, sqrt(dt)=2 m, exact prism data, u + g_z (CRN, h=2 m)",
+                   "stations": S, "paths_per_station": prob.paths_per_station, "dt": prob.dt,
+                   "precision": precision_name, "steps_per_pass": steps_per_pass},
+        "roofline": roof,
+        "station_estimates_per_s": est,
+    }
+
+    if precision_name == "f64":
+        # the mixed-precision kernel on the same workload, outside the timed region
+        pm = F.make_params(prob, precision=W.PREC_MIXED_F64ACC)
+        out_u2, out_g2 = F.alloc_stats(S), F.alloc_stats(S)
+        F.fk_solve_potential(P.stations, P.box, P.source, P.bc, pm, out_u2, ws_u)
+        F.fk_solve_gz(P.stations, P.box, P.source, P.bc, pm, out_g2, ws_g)
+        torch.cuda.synchronize()
+        m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        m0.record()
+        for _ in range(K):
+            F.fk_solve_potential(P.stations, P.box, P.source, P.bc, pm, out_u2, ws_u)
+            F.fk_solve_gz(P.stations, P.box, P.source, P.bc, pm, out_g2, ws_g)
+        m1.record()
+        torch.cuda.synchronize()
+        mu, mg = F.stats_to_numpy(out_u2)[:S], F.stats_to_numpy(out_g2)[:S]
+        msteps = int(mu["sum_steps"].sum()) + int(mg["sum_steps"].sum())
+        mval = msteps * K / (m0.elapsed_time(m1) / 1e3)
+        du = float(np.max(np.abs(mu["mean"] - su["mean"]) / su["se"]))
+        dg = float(np.max(np.abs(mg["mean"] - sg["mean"]) / sg["se"]))
+        result["mixed"] = {"value": mval, "unit": "Brownian steps/s", "speedup_vs_f64": mval / value,
+                           "max_abs_diff_vs_f64_in_se": {"u": du, "g_z": dg}}
+
+    if want_cpu:
+        result["cpu_baseline"] = cpu_baseline(prob, cpu_seconds)
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["f64", "mixed"], default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 (the multi-GPU design -- path "
+              "ranges per GPU merged by an all-gather of per-station statistics -- is described in DESIGN.md "
+              "and not implemented)", file=sys.stderr, flush=True)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr, flush=True)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    res = run(a.precision, max(1, a.steps), max(0, a.warmup), a.cpu_seconds, not a.no_cpu_baseline)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,812 @@
+// fk_api.cpp -- host runtime behind the C interface of fkgrav.h: argument
+// checks, workspace layout, launch planning and the enqueueing of the walk
+// and reduction kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "fk_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fk_status fail(fk_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+fk_status fail(fk_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+constexpr int64_t kChunk = 8192;             // samples per reduction partial
+constexpr int64_t kMaxPathIndex = 1ll << 32; // the path word of the counter is 32 bits
+
+std::mutex g_mu;
+
+// Walk-kernel timing: per-thread event pairs recorded around walk launches.
+struct Timing {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spare;
+    ~Timing()
+    {
+        for (auto& p : pending) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+        for (auto& p : spare) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+    }
+};
+thread_local Timing g_timing;
+constexpr size_t kMaxTimed = 256;
+
+bool timing_pair(std::pair<hipEvent_t, hipEvent_t>* out)
+{
+    if (!g_timing.spare.empty()) {
+        *out = g_timing.spare.back();
+        g_timing.spare.pop_back();
+        return true;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) return false;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return false;
+    }
+    *out = {a, b};
+    return true;
+}
+fk_launch g_launch[3] = {{256, 0, 32, 0}, {256, 0, 32, 0}, {256, 0, 32, 0}};
+
+int g_cus[64] = {0};
+
+int compute_units(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (dev < 0 || dev >= 64) return 0;
+    if (g_cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        g_cus[dev] = n;
+    }
+    return g_cus[dev];
+}
+
+bool timing_begin(std::pair<hipEvent_t, hipEvent_t>* ev, hipStream_t stream)
+{
+    if (!g_timing.on || !timing_pair(ev)) return false;
+    (void)hipEventRecord(ev->first, stream);
+    return true;
+}
+
+void timing_end(const std::pair<hipEvent_t, hipEvent_t>& ev, hipStream_t stream)
+{
+    (void)hipEventRecord(ev.second, stream);
+    if (g_timing.pending.size() >= kMaxTimed) {
+        g_timing.spare.push_back(g_timing.pending.front());
+        g_timing.pending.erase(g_timing.pending.begin());
+    }
+    g_timing.pending.push_back(ev);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    int64_t n_tasks;
+    int64_t n_chunks;
+    size_t values, steps, exits, partials, queue, total;
+};
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+fk_status check_params(int32_t kind, int64_t n_stations, const fk_params* p)
+{
+    if (kind != 0 && kind != 1) return fail(FK_EINVAL, "kind must be 0 (potential) or 1 (g_z), got %d", kind);
+    if (!p) return fail(FK_EINVAL, "params is NULL");
+    if (n_stations < 0) return fail(FK_EINVAL, "n_stations < 0");
+    if (p->paths_per_station < 2) return fail(FK_EINVAL, "paths_per_station must be >= 2");
+    if (p->path_offset < 0 || p->path_offset + p->paths_per_station > kMaxPathIndex)
+        return fail(FK_EUNSUPPORTED, "path_offset + paths_per_station must lie in [0, 2^32]");
+    if (!(is_finite(p->dt) && p->dt > 0.0)) return fail(FK_EINVAL, "dt must be finite and > 0");
+    if (!is_finite(p->G)) return fail(FK_EINVAL, "G must be finite");
+    if (!(is_finite(p->h) && p->h >= 0.0)) return fail(FK_EINVAL, "h must be finite and >= 0");
+    if (p->precision < 0 || p->precision > 2) return fail(FK_EINVAL, "unknown precision %d", p->precision);
+    if (p->exit_rule < 0 || p->exit_rule > 1) return fail(FK_EINVAL, "unknown exit_rule %d", p->exit_rule);
+    if (p->pairing < 0 || p->pairing > 1) return fail(FK_EINVAL, "unknown pairing %d", p->pairing);
+    if (p->max_steps < 1 || p->max_steps > 0x7fffffffll) return fail(FK_EINVAL, "max_steps must lie in [1, 2^31-1]");
+    const int64_t npair = kind == 1 ? 2 : 1;
+    if (n_stations > 0 && p->paths_per_station > (INT64_MAX / 16) / (npair * n_stations))
+        return fail(FK_EUNSUPPORTED, "n_stations * paths_per_station too large");
+    if (kind == 1 && p->pairing == FK_PAIR_INDEPENDENT && n_stations > (1ll << 31))
+        return fail(FK_EUNSUPPORTED, "independent pairing needs 2 * n_stations < 2^32");
+    if (n_stations > (1ll << 32)) return fail(FK_EUNSUPPORTED, "n_stations must be < 2^32");
+    return FK_OK;
+}
+
+Layout make_layout(int32_t kind, int64_t n_stations, const fk_params* p)
+{
+    Layout L{};
+    L.n_tasks = n_stations * p->paths_per_station * (kind == 1 ? 2 : 1);
+    L.n_chunks = (p->paths_per_station + kChunk - 1) / kChunk;
+    L.values = 0;
+    L.steps = align256(L.values + sizeof(double) * (size_t)L.n_tasks);
+    L.exits = align256(L.steps + sizeof(uint32_t) * (size_t)L.n_tasks);
+    L.partials = align256(L.exits + sizeof(fk::ExitRecord) * (size_t)L.n_tasks);
+    L.queue = align256(L.partials + sizeof(fk::Partial) * (size_t)(n_stations * L.n_chunks));
+    L.total = align256(L.queue + 256);
+    return L;
+}
+
+fk_status check_box(const fk_box* b)
+{
+    if (!b) return fail(FK_EINVAL, "box is NULL");
+    for (int c = 0; c < 3; ++c) {
+        if (!is_finite(b->lo[c]) || !is_finite(b->hi[c])) return fail(FK_EINVAL, "box bounds must be finite");
+        if (!(b->lo[c] < b->hi[c])) return fail(FK_EINVAL, "box lo[%d] must be < hi[%d]", c, c);
+    }
+    return FK_OK;
+}
+
+fk_status check_source(const fk_source* s)
+{
+    if (!s) return fail(FK_EINVAL, "source is NULL");
+    if (s->rho) {
+        int64_t nv = 1;
+        for (int c = 0; c < 3; ++c) {
+            if (s->n[c] < 1) return fail(FK_EINVAL, "grid size n[%d] must be >= 1", c);
+            if (s->n[c] > (1 << 24)) return fail(FK_EUNSUPPORTED, "grid size n[%d] must be <= 2^24", c);
+            if (!(is_finite(s->spacing[c]) && s->spacing[c] > 0.0)) return fail(FK_EINVAL, "grid spacing must be > 0");
+            if (!is_finite(s->origin[c])) return fail(FK_EINVAL, "grid origin must be finite");
+            nv *= s->n[c];
+        }
+        if (nv > (1ll << 31) - 1) return fail(FK_EUNSUPPORTED, "grid has more than 2^31-1 voxels");
+    }
+    if (s->n_prisms < 0 || s->n_prisms > FK_MAX_PRISMS)
+        return fail(FK_EUNSUPPORTED, "n_prisms must lie in [0, %d]", FK_MAX_PRISMS);
+    if (s->n_spheres < 0 || s->n_spheres > FK_MAX_SPHERES)
+        return fail(FK_EUNSUPPORTED, "n_spheres must lie in [0, %d]", FK_MAX_SPHERES);
+    if (s->n_prisms > 0 && !s->prisms) return fail(FK_EINVAL, "prisms is NULL");
+    if (s->n_spheres > 0 && !s->spheres) return fail(FK_EINVAL, "spheres is NULL");
+    for (int j = 0; j < s->n_prisms * 7; ++j)
+        if (!is_finite(s->prisms[j])) return fail(FK_EINVAL, "prism rows must be finite");
+    for (int j = 0; j < s->n_spheres * 5; ++j)
+        if (!is_finite(s->spheres[j])) return fail(FK_EINVAL, "sphere rows must be finite");
+    return FK_OK;
+}
+
+fk_status check_bc(const fk_boundary* bc)
+{
+    if (!bc) return fail(FK_EINVAL, "bc is NULL");
+    switch (bc->kind) {
+    case FK_BC_ZERO:
+        return FK_OK;
+    case FK_BC_QUADRATIC:
+        if (!bc->data) return fail(FK_EINVAL, "quadratic data is NULL");
+        for (int j = 0; j < 10; ++j)
+            if (!is_finite(bc->data[j])) return fail(FK_EINVAL, "quadratic coefficients must be finite");
+        return FK_OK;
+    case FK_BC_POINT_MASSES:
+    case FK_BC_PRISMS: {
+        if (bc->n_items < 1 || bc->n_items > FK_MAX_BC_ITEMS)
+            return fail(FK_EUNSUPPORTED, "boundary rows must lie in [1, %d]", FK_MAX_BC_ITEMS);
+        if (!bc->data) return fail(FK_EINVAL, "boundary data is NULL");
+        const int w = bc->kind == FK_BC_PRISMS ? 7 : 4;
+        for (int64_t j = 0; j < bc->n_items * w; ++j)
+            if (!is_finite(bc->data[j])) return fail(FK_EINVAL, "boundary rows must be finite");
+        return FK_OK;
+    }
+    case FK_BC_FACE_GRID:
+        if (!bc->data) return fail(FK_EINVAL, "face grid data is NULL");
+        for (int f = 0; f < 6; ++f)
+            if (bc->face_n[f][0] < 2 || bc->face_n[f][1] < 2)
+                return fail(FK_EINVAL, "face grids need at least 2 x 2 nodes (face %d)", f);
+        return FK_OK;
+    default:
+        return fail(FK_EINVAL, "unknown boundary kind %d", bc->kind);
+    }
+}
+
+bool power_of_two(double v)
+{
+    int e = 0;
+    return std::frexp(v, &e) == 0.5;
+}
+
+void fill_common(fk::WalkCommon& C, int32_t kind, const double* stations, int64_t n_stations, const fk_box* box,
+                 const fk_params* p, const Layout& L, char* ws)
+{
+    std::memset(&C, 0, sizeof C);
+    C.stations = stations;
+    if (ws) {
+        C.exits = reinterpret_cast<fk::ExitRecord*>(ws + L.exits);
+        C.steps = reinterpret_cast<uint32_t*>(ws + L.steps);
+        C.queue = reinterpret_cast<unsigned long long*>(ws + L.queue);
+    }
+    C.n_stations = n_stations;
+    C.N = p->paths_per_station;
+    C.n_tasks = L.n_tasks;
+    C.path_offset = p->path_offset;
+    C.max_steps = p->max_steps;
+    for (int c = 0; c < 3; ++c) {
+        C.lo[c] = box->lo[c];
+        C.hi[c] = box->hi[c];
+        C.lo_f[c] = (float)box->lo[c];
+        C.hi_f[c] = (float)box->hi[c];
+    }
+    C.sdt = std::sqrt(p->dt);
+    C.sdt_f = (float)C.sdt;
+    C.w = 2.0 * M_PI * p->G * (0.5 * p->dt);
+    C.G = p->G;
+    C.h = p->h > 0.0 ? p->h : std::sqrt(p->dt);
+    C.key0 = (uint32_t)(p->seed & 0xffffffffull);
+    C.key1 = (uint32_t)(p->seed >> 32);
+    C.problem_id = p->problem_id;
+    C.npair = kind == 1 ? 2 : 1;
+    C.pairing = p->pairing;
+    C.exit_rule = p->exit_rule;
+}
+
+void fill_bc(fk::BoundaryArgs& B, const fk_boundary* bc)
+{
+    std::memset(&B, 0, sizeof B);
+    B.kind = bc->kind;
+    if (bc->kind == FK_BC_QUADRATIC) {
+        for (int j = 0; j < 10; ++j) B.quad[j] = bc->data[j];
+    } else if (bc->kind == FK_BC_POINT_MASSES || bc->kind == FK_BC_PRISMS) {
+        const int w = bc->kind == FK_BC_PRISMS ? 7 : 4;
+        B.n_items = (int32_t)bc->n_items;
+        for (int64_t j = 0; j < bc->n_items; ++j)
+            for (int c = 0; c < w; ++c) B.items[j][c] = bc->data[j * w + c];
+    } else if (bc->kind == FK_BC_FACE_GRID) {
+        B.face_data = bc->data;
+        int64_t off = 0;
+        for (int f = 0; f < 6; ++f) {
+            B.face_n[f][0] = bc->face_n[f][0];
+            B.face_n[f][1] = bc->face_n[f][1];
+            B.face_off[f] = off;
+            off += (int64_t)bc->face_n[f][0] * bc->face_n[f][1];
+        }
+    }
+}
+
+void fill_source_f64(fk::SourceF64& S, const fk_source* s)
+{
+    std::memset(&S, 0, sizeof S);
+    S.rho = s->rho;
+    S.has_grid = s->rho != nullptr;
+    for (int c = 0; c < 3; ++c) {
+        S.n[c] = s->rho ? s->n[c] : 0;
+        S.origin[c] = s->origin[c];
+        S.spacing[c] = s->rho ? s->spacing[c] : 1.0;
+        S.inv[c] = 1.0 / S.spacing[c];
+        S.exact[c] = power_of_two(S.spacing[c]);
+    }
+    S.n_prisms = s->n_prisms;
+    S.n_spheres = s->n_spheres;
+    for (int j = 0; j < s->n_prisms; ++j)
+        for (int c = 0; c < 7; ++c) S.prisms[j][c] = s->prisms[7 * j + c];
+    for (int j = 0; j < s->n_spheres; ++j)
+        for (int c = 0; c < 5; ++c) S.spheres[j][c] = s->spheres[5 * j + c];
+}
+
+void fill_source_f32(fk::SourceF32& S, const fk_source* s)
+{
+    std::memset(&S, 0, sizeof S);
+    S.rho = s->rho;
+    S.has_grid = s->rho != nullptr;
+    for (int c = 0; c < 3; ++c) {
+        S.n[c] = s->rho ? s->n[c] : 0;
+        S.nf[c] = (float)S.n[c];
+        S.origin[c] = (float)s->origin[c];
+        S.inv[c] = s->rho ? (float)(1.0 / s->spacing[c]) : 1.0f;
+    }
+    S.n_prisms = s->n_prisms;
+    S.n_spheres = s->n_spheres;
+    for (int j = 0; j < s->n_prisms; ++j)
+        for (int c = 0; c < 7; ++c) S.prisms[j][c] = (float)s->prisms[7 * j + c];
+    for (int j = 0; j < s->n_spheres; ++j)
+        for (int c = 0; c < 5; ++c) S.spheres[j][c] = (float)s->spheres[5 * j + c];
+}
+
+fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false)
+{
+    fk_launch l;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        l = g_launch[precision];
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(FK_EDEVICE, "hipGetDevice failed");
+    const int cus = compute_units(dev);
+    if (cus <= 0) return fail(FK_EDEVICE, "could not query the compute-unit count");
+    int bpc = l.blocks_per_cu;
+    if (bpc <= 0) {
+        const hipError_t oe = batch ? fk::batch_occupancy(precision, l.block, &bpc)
+                                    : fk::walk_occupancy(precision, l.block, &bpc);
+        if (oe != hipSuccess || bpc <= 0)
+            return fail(FK_EDEVICE, "occupancy query failed for block %d", l.block);
+    }
+    int64_t grid = (int64_t)cus * bpc;
+    const int64_t need = (n_tasks + l.block - 1) / l.block;
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    cfg->block = l.block;
+    cfg->grid = (int)grid;
+    cfg->grab = l.grab;
+    return FK_OK;
+}
+
+fk_status solve(int32_t kind, const double* stations, int64_t n_stations, const fk_box* box, const fk_source* src,
+                const fk_boundary* bc, const fk_params* p, fk_stat* out, void* workspace, size_t workspace_bytes,
+                void* hip_stream)
+{
+    fk_status st;
+    if ((st = check_params(kind, n_stations, p)) != FK_OK) return st;
+    if ((st = check_box(box)) != FK_OK) return st;
+    if ((st = check_source(src)) != FK_OK) return st;
+    if ((st = check_bc(bc)) != FK_OK) return st;
+    if (n_stations == 0) return FK_OK;
+    if (!stations) return fail(FK_EINVAL, "stations is NULL");
+    if (!out) return fail(FK_EINVAL, "out is NULL");
+    const Layout L = make_layout(kind, n_stations, p);
+    if (!workspace) return fail(FK_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FK_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (workspace_bytes < L.total)
+        return fail(FK_EWORKSPACE, "workspace has %zu bytes, %zu needed", workspace_bytes, L.total);
+    if (kind == 1) {
+        const double h = p->h > 0.0 ? p->h : std::sqrt(p->dt);
+        if (!(h > 0.0)) return fail(FK_EINVAL, "difference step h must be > 0");
+    }
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    char* ws = static_cast<char*>(workspace);
+
+    fk::LaunchCfg cfg;
+    if ((st = plan_launch(p->precision, L.n_tasks, &cfg)) != FK_OK) return st;
+
+    fk::WalkCommon C;
+    fill_common(C, kind, stations, n_stations, box, p, L, ws);
+    C.grab = cfg.grab;
+    C.total_waves = (uint32_t)((int64_t)cfg.grid * cfg.block / 64);
+
+    hipError_t e = fk::launch_zero_queue(C.queue, stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "queue reset launch failed: %s", hipGetErrorString(e));
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    const bool timed = timing_begin(&ev, stream);
+    if (p->precision == FK_F64) {
+        fk::WalkArgsF64 A;
+        A.c = C;
+        fill_source_f64(A.src, src);
+        e = fk::launch_walk_f64(A, cfg, stream);
+    } else {
+        fk::WalkArgsF32 A;
+        A.c = C;
+        fill_source_f32(A.src, src);
+        e = fk::launch_walk_f32(A, p->precision == FK_MIXED_KAHAN, cfg, stream);
+    }
+    if (timed) timing_end(ev, stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "walk launch failed: %s", hipGetErrorString(e));
+
+    fk::ReduceArgs R;
+    std::memset(&R, 0, sizeof R);
+    R.exits = C.exits;
+    R.values = reinterpret_cast<double*>(ws + L.values);
+    R.steps = C.steps;
+    R.partials = reinterpret_cast<fk::Partial*>(ws + L.partials);
+    R.out = out;
+    R.n_stations = n_stations;
+    R.N = p->paths_per_station;
+    R.chunk = kChunk;
+    R.n_chunks = L.n_chunks;
+    R.npair = C.npair;
+    R.two_h = 2.0 * C.h;
+    R.w = C.w;
+    R.G = C.G;
+    for (int c = 0; c < 3; ++c) {
+        R.lo[c] = C.lo[c];
+        R.hi[c] = C.hi[c];
+    }
+    fill_bc(R.bc, bc);
+    e = fk::launch_reduce(R, stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "reduction launch failed: %s", hipGetErrorString(e));
+    return FK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves.
+// ---------------------------------------------------------------------------
+struct BatchLayout {
+    size_t desc, task_off, block_off, queue, total;
+    std::vector<Layout> per;       // per-problem layouts relative to base[m]
+    std::vector<size_t> base;
+    int64_t n_tasks = 0, n_blocks = 0, n_stations = 0;
+};
+
+static_assert(sizeof(fk::BatchDesc) % 8 == 0, "descriptor must be whole 64-bit words");
+
+fk_status check_batch(const fk_problem* probs, int32_t n)
+{
+    if (n < 0 || n > FK_MAX_BATCH) return fail(FK_EUNSUPPORTED, "n_problems must lie in [0, %d]", FK_MAX_BATCH);
+    if (n > 0 && !probs) return fail(FK_EINVAL, "problems is NULL");
+    fk_status st;
+    for (int32_t m = 0; m < n; ++m) {
+        const fk_problem& P = probs[m];
+        if ((st = check_params(P.kind, P.n_stations, &P.params)) != FK_OK) return st;
+        if ((st = check_box(&P.box)) != FK_OK) return st;
+        if ((st = check_source(&P.source)) != FK_OK) return st;
+        if ((st = check_bc(&P.bc)) != FK_OK) return st;
+        if (P.n_stations > 0 && !P.stations) return fail(FK_EINVAL, "problem %d: stations is NULL", m);
+        if (P.out_offset < 0) return fail(FK_EINVAL, "problem %d: out_offset < 0", m);
+        if (P.params.precision != probs[0].params.precision)
+            return fail(FK_EINVAL, "problem %d: all problems of a batch need the same precision", m);
+    }
+    return FK_OK;
+}
+
+BatchLayout make_batch_layout(const fk_problem* probs, int32_t n)
+{
+    BatchLayout B;
+    B.desc = 0;
+    B.task_off = align256(B.desc + sizeof(fk::BatchDesc) * (size_t)n);
+    B.block_off = align256(B.task_off + sizeof(int64_t) * (size_t)(n + 1));
+    size_t at = align256(B.block_off + sizeof(int64_t) * (size_t)(n + 1));
+    for (int32_t m = 0; m < n; ++m) {
+        const Layout L = make_layout(probs[m].kind, probs[m].n_stations, &probs[m].params);
+        B.per.push_back(L);
+        B.base.push_back(at);
+        at = align256(at + L.queue);       // the per-problem queue slot is not used in a batch
+        B.n_tasks += L.n_tasks;
+        B.n_blocks += probs[m].n_stations * L.n_chunks;
+        B.n_stations += probs[m].n_stations;
+    }
+    B.queue = at;
+    B.total = align256(at + 256);
+    return B;
+}
+
+fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* workspace, size_t workspace_bytes,
+                      void* hip_stream)
+{
+    fk_status st;
+    if ((st = check_batch(probs, n)) != FK_OK) return st;
+    const BatchLayout BL = make_batch_layout(probs, n);
+    if (BL.n_tasks == 0) return FK_OK;
+    if (!out) return fail(FK_EINVAL, "out is NULL");
+    if (!workspace) return fail(FK_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FK_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (workspace_bytes < BL.total)
+        return fail(FK_EWORKSPACE, "workspace has %zu bytes, %zu needed", workspace_bytes, BL.total);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    char* ws = static_cast<char*>(workspace);
+    const int precision = probs[0].params.precision;
+
+    fk::LaunchCfg cfg;
+    if ((st = plan_launch(precision, BL.n_tasks, &cfg, true)) != FK_OK) return st;
+
+    std::vector<int64_t> task_off(n + 1, 0), block_off(n + 1, 0);
+    int64_t station_base = 0;
+    auto* descs = reinterpret_cast<fk::BatchDesc*>(ws + BL.desc);
+    hipError_t e = fk::launch_zero_queue(reinterpret_cast<unsigned long long*>(ws + BL.queue), stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "queue reset launch failed: %s", hipGetErrorString(e));
+    for (int32_t m = 0; m < n; ++m) {
+        const fk_problem& P = probs[m];
+        const Layout& L = BL.per[m];
+        char* pb = ws + BL.base[m];
+        fk::BatchDesc D;
+        std::memset(&D, 0, sizeof D);
+        fill_common(D.c, P.kind, P.stations, P.n_stations, &P.box, &P.params, L, pb);
+        D.c.queue = nullptr;
+        if (precision == FK_F64) fill_source_f64(D.s64, &P.source);
+        else fill_source_f32(D.s32, &P.source);
+        fill_bc(D.bc, &P.bc);
+        D.values = reinterpret_cast<double*>(pb + L.values);
+        D.partials = reinterpret_cast<fk::Partial*>(pb + L.partials);
+        D.out = out + P.out_offset;
+        D.n_chunks = L.n_chunks;
+        D.task_base = task_off[m];
+        D.block_base = block_off[m];
+        D.station_base = station_base;
+        task_off[m + 1] = task_off[m] + L.n_tasks;
+        block_off[m + 1] = block_off[m] + P.n_stations * L.n_chunks;
+        station_base += P.n_stations;
+        e = fk::launch_write_words(reinterpret_cast<uint64_t*>(descs + m), reinterpret_cast<const uint64_t*>(&D),
+                                   (int64_t)(sizeof D / 8), stream);
+        if (e != hipSuccess) return fail(FK_EDEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
+    }
+    e = fk::launch_write_words(reinterpret_cast<uint64_t*>(ws + BL.task_off),
+                               reinterpret_cast<const uint64_t*>(task_off.data()), n + 1, stream);
+    if (e == hipSuccess)
+        e = fk::launch_write_words(reinterpret_cast<uint64_t*>(ws + BL.block_off),
+                                   reinterpret_cast<const uint64_t*>(block_off.data()), n + 1, stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "offset upload failed: %s", hipGetErrorString(e));
+
+    fk::BatchArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.desc = descs;
+    A.task_off = reinterpret_cast<const int64_t*>(ws + BL.task_off);
+    A.block_off = reinterpret_cast<const int64_t*>(ws + BL.block_off);
+    A.queue = reinterpret_cast<unsigned long long*>(ws + BL.queue);
+    A.n_tasks = BL.n_tasks;
+    A.n_problems = n;
+    A.grab = cfg.grab;
+    A.total_waves = (uint32_t)((int64_t)cfg.grid * cfg.block / 64);
+    A.precision = precision;
+    A.chunk = kChunk;
+
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    const bool timed = timing_begin(&ev, stream);
+    e = fk::launch_batch_walk(A, cfg, stream);
+    if (timed) timing_end(ev, stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "batch walk launch failed: %s", hipGetErrorString(e));
+    e = fk::launch_batch_reduce(A, BL.n_blocks, BL.n_stations, stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "batch reduction launch failed: %s", hipGetErrorString(e));
+    return FK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (vector-Jacobian product with respect to the voxel densities).
+// ---------------------------------------------------------------------------
+struct AdjLayout {
+    int64_t nvox;
+    size_t counts, queue, total;
+};
+
+AdjLayout make_adj_layout(int64_t n_stations, const fk_source* src)
+{
+    AdjLayout A{};
+    A.nvox = (int64_t)src->n[0] * src->n[1] * src->n[2];
+    A.counts = 0;
+    A.queue = align256(sizeof(int64_t) * (size_t)(n_stations * A.nvox));
+    A.total = align256(A.queue + 256);
+    return A;
+}
+
+fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, const fk_box* box, const fk_source* src,
+                  const fk_boundary* bc, const fk_params* p, const fk_stat* fwd_out, const void* fwd_workspace,
+                  size_t fwd_workspace_bytes, const double* grad_out, double* grad_rho, void* workspace,
+                  size_t workspace_bytes, void* hip_stream)
+{
+    fk_status st;
+    if ((st = check_params(kind, n_stations, p)) != FK_OK) return st;
+    if ((st = check_box(box)) != FK_OK) return st;
+    if ((st = check_source(src)) != FK_OK) return st;
+    if ((st = check_bc(bc)) != FK_OK) return st;
+    if (!src->rho) return fail(FK_EINVAL, "the adjoint needs a voxel grid (source.rho is NULL)");
+    if (!grad_rho) return fail(FK_EINVAL, "grad_rho is NULL");
+    const AdjLayout AL = make_adj_layout(n_stations, src);
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (n_stations == 0) {
+        hipError_t e = fk::launch_fill_zero(reinterpret_cast<int64_t*>(grad_rho), AL.nvox, stream);
+        return e == hipSuccess ? FK_OK : fail(FK_EDEVICE, "fill launch failed: %s", hipGetErrorString(e));
+    }
+    if (!stations || !fwd_out || !fwd_workspace || !grad_out) return fail(FK_EINVAL, "NULL input pointer");
+    const Layout L = make_layout(kind, n_stations, p);
+    if (fwd_workspace_bytes < L.total)
+        return fail(FK_EWORKSPACE, "forward workspace has %zu bytes, %zu expected", fwd_workspace_bytes, L.total);
+    if (!workspace) return fail(FK_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FK_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (workspace_bytes < AL.total)
+        return fail(FK_EWORKSPACE, "workspace has %zu bytes, %zu needed", workspace_bytes, AL.total);
+    char* ws = static_cast<char*>(workspace);
+    int64_t* counts = reinterpret_cast<int64_t*>(ws + AL.counts);
+
+    fk::LaunchCfg cfg;
+    if ((st = plan_launch(p->precision, L.n_tasks, &cfg)) != FK_OK) return st;
+    fk::WalkCommon C;
+    fill_common(C, kind, stations, n_stations, box, p, L, nullptr);
+    C.exits = nullptr;
+    C.steps = nullptr;
+    C.queue = reinterpret_cast<unsigned long long*>(ws + AL.queue);
+    C.grab = cfg.grab;
+    C.total_waves = (uint32_t)((int64_t)cfg.grid * cfg.block / 64);
+    C.counts = counts;
+    C.fwd_steps = reinterpret_cast<const uint32_t*>(static_cast<const char*>(fwd_workspace) + L.steps);
+    C.nvox = AL.nvox;
+
+    hipError_t e = fk::launch_fill_zero(counts, n_stations * AL.nvox, stream);
+    if (e == hipSuccess) e = fk::launch_zero_queue(C.queue, stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "adjoint set-up launch failed: %s", hipGetErrorString(e));
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    const bool timed = timing_begin(&ev, stream);
+    if (p->precision == FK_F64) {
+        fk::WalkArgsF64 A;
+        A.c = C;
+        fill_source_f64(A.src, src);
+        e = fk::launch_walk_f64(A, cfg, stream, true);
+    } else {
+        fk::WalkArgsF32 A;
+        A.c = C;
+        fill_source_f32(A.src, src);
+        e = fk::launch_walk_f32(A, p->precision == FK_MIXED_KAHAN, cfg, stream, true);
+    }
+    if (timed) timing_end(ev, stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "adjoint walk launch failed: %s", hipGetErrorString(e));
+    // d u_p / d rho_v = -2 pi G (dt/2) c_v; a g_z sample divides by 2h
+    const double scale = -C.w / (kind == 1 ? 2.0 * C.h : 1.0);
+    e = fk::launch_adjoint_combine(counts, n_stations, AL.nvox, grad_out, fwd_out, scale, grad_rho, stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "adjoint combine launch failed: %s", hipGetErrorString(e));
+    return FK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fk_adjoint_workspace_bytes(int64_t n_stations, const fk_source* source)
+{
+    if (n_stations < 0 || !source || check_source(source) != FK_OK || !source->rho) return 0;
+    return make_adj_layout(n_stations, source).total;
+}
+
+fk_status fk_potential_adjoint(const double* stations, int64_t n_stations, const fk_box* box,
+                               const fk_source* source, const fk_boundary* bc, const fk_params* params,
+                               const fk_stat* forward_out, const void* forward_workspace,
+                               size_t forward_workspace_bytes, const double* grad_out, double* grad_rho,
+                               void* workspace, size_t workspace_bytes, void* hip_stream)
+{
+    return adjoint(0, stations, n_stations, box, source, bc, params, forward_out, forward_workspace,
+                   forward_workspace_bytes, grad_out, grad_rho, workspace, workspace_bytes, hip_stream);
+}
+
+fk_status fk_gz_adjoint(const double* stations, int64_t n_stations, const fk_box* box, const fk_source* source,
+                        const fk_boundary* bc, const fk_params* params, const fk_stat* forward_out,
+                        const void* forward_workspace, size_t forward_workspace_bytes, const double* grad_out,
+                        double* grad_rho, void* workspace, size_t workspace_bytes, void* hip_stream)
+{
+    return adjoint(1, stations, n_stations, box, source, bc, params, forward_out, forward_workspace,
+                   forward_workspace_bytes, grad_out, grad_rho, workspace, workspace_bytes, hip_stream);
+}
+
+size_t fk_batch_workspace_bytes(const fk_problem* problems, int32_t n_problems)
+{
+    if (check_batch(problems, n_problems) != FK_OK) return 0;
+    return make_batch_layout(problems, n_problems).total;
+}
+
+fk_status fk_batch_layout(const fk_problem* problems, int32_t n_problems, int32_t m, size_t* values_offset,
+                          size_t* steps_offset)
+{
+    fk_status st = check_batch(problems, n_problems);
+    if (st != FK_OK) return st;
+    if (m < 0 || m >= n_problems) return fail(FK_EINVAL, "problem index %d out of range", m);
+    const BatchLayout B = make_batch_layout(problems, n_problems);
+    if (values_offset) *values_offset = B.base[m] + B.per[m].values;
+    if (steps_offset) *steps_offset = B.base[m] + B.per[m].steps;
+    return FK_OK;
+}
+
+fk_status fk_solve_batch(const fk_problem* problems, int32_t n_problems, fk_stat* out, void* workspace,
+                         size_t workspace_bytes, void* hip_stream)
+{
+    return solve_batch(problems, n_problems, out, workspace, workspace_bytes, hip_stream);
+}
+
+
+size_t fk_workspace_bytes(int32_t kind, int64_t n_stations, const fk_params* params)
+{
+    if (check_params(kind, n_stations, params) != FK_OK) return 0;
+    return make_layout(kind, n_stations, params).total;
+}
+
+fk_status fk_workspace_layout(int32_t kind, int64_t n_stations, const fk_params* params, size_t* values_offset,
+                              size_t* steps_offset, size_t* total_bytes)
+{
+    fk_status st = check_params(kind, n_stations, params);
+    if (st != FK_OK) return st;
+    const Layout L = make_layout(kind, n_stations, params);
+    if (values_offset) *values_offset = L.values;
+    if (steps_offset) *steps_offset = L.steps;
+    if (total_bytes) *total_bytes = L.total;
+    return FK_OK;
+}
+
+fk_status fk_check_stations(const double* stations_host, int64_t n_stations, const fk_box* box, int32_t kind,
+                            const fk_params* params)
+{
+    fk_status st;
+    if ((st = check_params(kind, n_stations, params)) != FK_OK) return st;
+    if ((st = check_box(box)) != FK_OK) return st;
+    if (n_stations > 0 && !stations_host) return fail(FK_EINVAL, "stations is NULL");
+    const double h = kind == 1 ? (params->h > 0.0 ? params->h : std::sqrt(params->dt)) : 0.0;
+    for (int64_t s = 0; s < n_stations; ++s) {
+        const double* x = stations_host + 3 * s;
+        for (int c = 0; c < 3; ++c) {
+            const double d = c == 2 ? h : 0.0;
+            if (!is_finite(x[c]) || !(x[c] - d > box->lo[c] && x[c] + d < box->hi[c]))
+                return fail(FK_EDOMAIN, "station %lld is not strictly inside the box%s", (long long)s,
+                            kind == 1 ? " (with +-h along z)" : "");
+        }
+    }
+    return FK_OK;
+}
+
+fk_status fk_solve_potential(const double* stations, int64_t n_stations, const fk_box* box, const fk_source* source,
+                             const fk_boundary* bc, const fk_params* params, fk_stat* out, void* workspace,
+                             size_t workspace_bytes, void* hip_stream)
+{
+    return solve(0, stations, n_stations, box, source, bc, params, out, workspace, workspace_bytes, hip_stream);
+}
+
+fk_status fk_solve_gz(const double* stations, int64_t n_stations, const fk_box* box, const fk_source* source,
+                      const fk_boundary* bc, const fk_params* params, fk_stat* out, void* workspace,
+                      size_t workspace_bytes, void* hip_stream)
+{
+    return solve(1, stations, n_stations, box, source, bc, params, out, workspace, workspace_bytes, hip_stream);
+}
+
+fk_status fk_set_launch(int32_t precision, const fk_launch* launch)
+{
+    if (precision < 0 || precision > 2) return fail(FK_EINVAL, "unknown precision %d", precision);
+    if (!launch) return fail(FK_EINVAL, "launch is NULL");
+    if (launch->block < 64 || launch->block > 256 || launch->block % 64 != 0)
+        return fail(FK_EINVAL, "block must be a multiple of 64 in [64, 256]");
+    if (launch->blocks_per_cu < 0 || launch->blocks_per_cu > 64) return fail(FK_EINVAL, "blocks_per_cu must lie in [0, 64]");
+    if (launch->grab < 1 || launch->grab > 64) return fail(FK_EINVAL, "grab must lie in [1, 64]");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_launch[precision] = *launch;
+    g_launch[precision].pad0 = 0;
+    return FK_OK;
+}
+
+fk_status fk_get_launch(int32_t precision, fk_launch* launch)
+{
+    if (precision < 0 || precision > 2) return fail(FK_EINVAL, "unknown precision %d", precision);
+    if (!launch) return fail(FK_EINVAL, "launch is NULL");
+    std::lock_guard<std::mutex> lk(g_mu);
+    *launch = g_launch[precision];
+    return FK_OK;
+}
+
+fk_status fk_timing_enable(int32_t on)
+{
+    g_timing.on = on != 0;
+    return FK_OK;
+}
+
+fk_status fk_timing_read(double* ms_out, int32_t max_n, int32_t* n_out)
+{
+    if (max_n < 0) return fail(FK_EINVAL, "max_n < 0");
+    if (max_n > 0 && !ms_out) return fail(FK_EINVAL, "ms_out is NULL");
+    int32_t n = 0;
+    fk_status st = FK_OK;
+    for (auto& p : g_timing.pending) {
+        if (hipEventSynchronize(p.second) != hipSuccess) st = fail(FK_EDEVICE, "hipEventSynchronize failed");
+        float ms = 0.0f;
+        if (st == FK_OK && hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess)
+            st = fail(FK_EDEVICE, "hipEventElapsedTime failed");
+        if (n < max_n) ms_out[n] = ms;
+        ++n;
+        g_timing.spare.push_back(p);
+    }
+    g_timing.pending.clear();
+    if (n_out) *n_out = n < max_n ? n : max_n;
+    return st;
+}
+
+const char* fk_status_string(int32_t status)
+{
+    switch (status) {
+    case FK_OK: return "ok";
+    case FK_EINVAL: return "invalid argument";
+    case FK_EDOMAIN: return "station not strictly inside the box";
+    case FK_EWORKSPACE: return "workspace too small or misaligned";
+    case FK_EDEVICE: return "HIP runtime error";
+    case FK_ETRUNC: return "walks hit max_steps";
+    case FK_EUNSUPPORTED: return "size limit exceeded";
+    default: return "unknown status";
+    }
+}
+
+const char* fk_last_error(void) { return g_last_error.c_str(); }
+
+int32_t fk_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+// fk_device.hpp -- device-side building blocks of the walk kernels for gfx950:
+// the Philox4x32-10 counter generator, the Box-Muller maps of the two random
+// streams, the density lookup, the exit test and exit point, and the
+// Dirichlet data read at the exit (arXiv:1709.07469, section 2.3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fk_internal.hpp"
+
+namespace fk {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round multiplies
+// words 0 and 2 by the Philox multipliers (32x32 -> 64), mixes the high halves
+// into words 1 and 3 with the round key and permutes; the key advances by the
+// Weyl increments.  The key is wave-uniform (it is the seed), so the key
+// schedule is scalar work.
+// ---------------------------------------------------------------------------
+struct Block {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Block philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Block{c0, c1, c2, c3};
+}
+
+// FP64 stream: one block -> two 53-bit uniforms in (0, 1] -> one Box-Muller
+// pair (cosine branch first).  The angle 2 pi U is evaluated as sincospi(2U),
+// which needs no reduction by pi.
+__device__ __forceinline__ void normals_f64(const Block& b, double& z0, double& z1)
+{
+    const uint64_t a = ((((uint64_t)b.w1) << 21) | (uint64_t)(b.w0 >> 11)) + 1ull;
+    const uint64_t c = ((((uint64_t)b.w3) << 21) | (uint64_t)(b.w2 >> 11)) + 1ull;
+    const double u1 = (double)a * 0x1p-53;
+    const double u2 = (double)c * 0x1p-53;
+    const double r = sqrt(-2.0 * log(u1));
+    double s, co;
+    sincospi(2.0 * u2, &s, &co);
+    z0 = r * co;
+    z1 = r * s;
+}
+
+// FP32 stream: two 24-bit uniforms in (0, 1] -> one Box-Muller pair, on the
+// hardware transcendental unit: v_log_f32 is log2, and v_sin_f32 / v_cos_f32
+// take their argument in revolutions, so sin(2 pi u) is one instruction.
+__device__ __forceinline__ void normals_f32(uint32_t wa, uint32_t wb, float& z0, float& z1)
+{
+    const float u1 = (float)((wa >> 8) + 1u) * 0x1p-24f;
+    const float u2 = (float)((wb >> 8) + 1u) * 0x1p-24f;
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));  // -2 ln 2 log2 u
+    z0 = r * __builtin_amdgcn_cosf(u2);
+    z1 = r * __builtin_amdgcn_sinf(u2);
+}
+
+// ---------------------------------------------------------------------------
+// Density rho(x): voxel grid (zero outside), then analytic prisms [lo, hi),
+// then open balls; contributions add in that order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double grid_axis_f64(double x, double o, double d, double inv, int exact)
+{
+    // floor((x - o) / d); when d is a power of two the reciprocal product is
+    // the same number as the quotient
+    const double q = exact ? (x - o) * inv : (x - o) / d;
+    return floor(q);
+}
+
+// Voxel holding (x, y, z), or -1 outside the grid (or without a grid).
+__device__ __forceinline__ int64_t voxel_f64(const SourceF64& s, double x, double y, double z)
+{
+    if (!s.has_grid) return -1;
+    const double tx = grid_axis_f64(x, s.origin[0], s.spacing[0], s.inv[0], s.exact[0]);
+    const double ty = grid_axis_f64(y, s.origin[1], s.spacing[1], s.inv[1], s.exact[1]);
+    const double tz = grid_axis_f64(z, s.origin[2], s.spacing[2], s.inv[2], s.exact[2]);
+    const bool in = tx >= 0.0 && tx < (double)s.n[0] && ty >= 0.0 && ty < (double)s.n[1] && tz >= 0.0 &&
+                    tz < (double)s.n[2];
+    return in ? ((int64_t)(int)tz * s.n[1] + (int)ty) * s.n[0] + (int)tx : -1;
+}
+
+// Density of the analytic bodies at (x, y, z), added to r in body order.
+__device__ __forceinline__ double bodies_f64(const SourceF64& s, double r, double x, double y, double z)
+{
+    for (int j = 0; j < s.n_prisms; ++j) {
+        const double* q = s.prisms[j];
+        if (x >= q[0] && x < q[3] && y >= q[1] && y < q[4] && z >= q[2] && z < q[5]) r = r + q[6];
+    }
+    for (int j = 0; j < s.n_spheres; ++j) {
+        const double* q = s.spheres[j];
+        const double dx = x - q[0], dy = y - q[1], dz = z - q[2];
+        if (dx * dx + dy * dy + dz * dz < q[3] * q[3]) r = r + q[4];
+    }
+    return r;
+}
+
+__device__ __forceinline__ double rho_f64(const SourceF64& s, double x, double y, double z)
+{
+    const int64_t v = voxel_f64(s, x, y, z);
+    const double r = v >= 0 ? 0.0 + (double)s.rho[v] : 0.0;
+    return bodies_f64(s, r, x, y, z);
+}
+
+__device__ __forceinline__ int voxel_f32(const SourceF32& s, float x, float y, float z)
+{
+    if (!s.has_grid) return -1;
+    const float tx = floorf((x - s.origin[0]) * s.inv[0]);
+    const float ty = floorf((y - s.origin[1]) * s.inv[1]);
+    const float tz = floorf((z - s.origin[2]) * s.inv[2]);
+    const bool in = tx >= 0.0f && tx < s.nf[0] && ty >= 0.0f && ty < s.nf[1] && tz >= 0.0f && tz < s.nf[2];
+    return in ? ((int)tz * s.n[1] + (int)ty) * s.n[0] + (int)tx : -1;
+}
+
+__device__ __forceinline__ float bodies_f32(const SourceF32& s, float r, float x, float y, float z)
+{
+    for (int j = 0; j < s.n_prisms; ++j) {
+        const float* q = s.prisms[j];
+        if (x >= q[0] && x < q[3] && y >= q[1] && y < q[4] && z >= q[2] && z < q[5]) r = r + q[6];
+    }
+    for (int j = 0; j < s.n_spheres; ++j) {
+        const float* q = s.spheres[j];
+        const float dx = x - q[0], dy = y - q[1], dz = z - q[2];
+        if (dx * dx + dy * dy + dz * dz < q[3] * q[3]) r = r + q[4];
+    }
+    return r;
+}
+
+__device__ __forceinline__ float rho_f32(const SourceF32& s, float x, float y, float z)
+{
+    const int v = voxel_f32(s, x, y, z);
+    const float r = v >= 0 ? 0.0f + s.rho[v] : 0.0f;
+    return bodies_f32(s, r, x, y, z);
+}
+
+// ---------------------------------------------------------------------------
+// Exit test (the boundary counts as outside) and the INTERSECT exit point.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ bool outside(const T* lo, const T* hi, T x, T y, T z)
+{
+    return x <= lo[0] || x >= hi[0] || y <= lo[1] || y >= hi[1] || z <= lo[2] || z >= hi[2];
+}
+
+// First face met on the segment a -> b (b outside, a inside): the crossing
+// fraction t_c = (face_c - a_c) / (b_c - a_c) is smallest (ties: lower axis);
+// the point is a + t (b - a) with the crossing coordinate set to the face.
+__device__ __forceinline__ void intersect_exit(const double* lo, const double* hi, const double a[3],
+                                               const double b[3], double e[3])
+{
+    double tmin = 2.0;
+    int cmin = 0;
+    double fmin = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const bool below = b[c] <= lo[c];
+        const bool above = b[c] >= hi[c];
+        if (below || above) {
+            const double f = below ? lo[c] : hi[c];
+            const double t = (f - a[c]) / (b[c] - a[c]);
+            if (t < tmin) {
+                tmin = t;
+                cmin = c;
+                fmin = f;
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) e[c] = fma(tmin, b[c] - a[c], a[c]);
+    e[cmin] = fmin;
+}
+
+// ---------------------------------------------------------------------------
+// Dirichlet data.
+// ---------------------------------------------------------------------------
+
+// ln(a + sqrt(a^2 + s)) with s = sum of the other two squares; for a < 0 the
+// sum a + r cancels, and a + r = s / (r - a) is used instead.
+__device__ __forceinline__ double log_shift(double a, double r, double s)
+{
+    return a >= 0.0 ? log(a + r) : log(s) - log(r - a);
+}
+
+// Newtonian integral of the unit-density prism [lo, hi] seen from p: the
+// alternating corner sum of
+//   XY ln(Z+r) + YZ ln(X+r) + ZX ln(Y+r)
+//   - X^2/2 atan(YZ/(Xr)) - Y^2/2 atan(ZX/(Yr)) - Z^2/2 atan(XY/(Zr))
+// with corner (X, Y, Z) = corner - p and sign + at the upper corner (Nagy,
+// Papp & Benedek 2000); a term whose prefactor is zero vanishes.
+__device__ inline double prism_newton(const double* q, double px, double py, double pz)
+{
+    double v = 0.0;
+    for (int corner = 0; corner < 8; ++corner) {
+        const double X = ((corner & 1) ? q[3] : q[0]) - px;
+        const double Y = ((corner & 2) ? q[4] : q[1]) - py;
+        const double Z = ((corner & 4) ? q[5] : q[2]) - pz;
+        const double X2 = X * X, Y2 = Y * Y, Z2 = Z * Z;
+        const double r = sqrt(X2 + Y2 + Z2);
+        double f = 0.0;
+        if (X * Y != 0.0) f += X * Y * log_shift(Z, r, X2 + Y2);
+        if (Y * Z != 0.0) f += Y * Z * log_shift(X, r, Y2 + Z2);
+        if (Z * X != 0.0) f += Z * X * log_shift(Y, r, Z2 + X2);
+        if (X != 0.0) f -= 0.5 * X2 * atan(Y * Z / (X * r));
+        if (Y != 0.0) f -= 0.5 * Y2 * atan(Z * X / (Y * r));
+        if (Z != 0.0) f -= 0.5 * Z2 * atan(X * Y / (Z * r));
+        // sign (-1)^(i+j+k) with index 1 = lower, 2 = upper corner: positive
+        // when the number of upper coordinates is odd
+        const int uppers = (corner & 1) + ((corner >> 1) & 1) + ((corner >> 2) & 1);
+        v += (uppers & 1) ? f : -f;
+    }
+    return v;
+}
+
+__device__ inline double face_grid(const BoundaryArgs& bc, const double* lo, const double* hi, const double e[3])
+{
+    int fc = 0, side = 0;
+    double best = -1.0 / 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double dl = lo[c] - e[c];
+        const double dh = e[c] - hi[c];
+        if (dl > best) { best = dl; fc = c; side = 0; }
+        if (dh > best) { best = dh; fc = c; side = 1; }
+    }
+    const int f = 2 * fc + side;
+    const int ax = (fc == 0) ? 1 : 0;
+    const int bx = (fc == 2) ? 1 : 2;
+    const int na = bc.face_n[f][0], nb = bc.face_n[f][1];
+    const double pa = fmin(fmax(e[ax], lo[ax]), hi[ax]);
+    const double pb = fmin(fmax(e[bx], lo[bx]), hi[bx]);
+    const double ta = (pa - lo[ax]) / (hi[ax] - lo[ax]) * (double)(na - 1);
+    const double tb = (pb - lo[bx]) / (hi[bx] - lo[bx]) * (double)(nb - 1);
+    int ia = (int)floor(ta), ib = (int)floor(tb);
+    ia = ia < 0 ? 0 : (ia > na - 2 ? na - 2 : ia);
+    ib = ib < 0 ? 0 : (ib > nb - 2 ? nb - 2 : ib);
+    const double fa = ta - ia, fb = tb - ib;
+    const double* d = bc.face_data + bc.face_off[f];
+    const double v00 = d[(int64_t)ib * na + ia], v10 = d[(int64_t)ib * na + ia + 1];
+    const double v01 = d[(int64_t)(ib + 1) * na + ia], v11 = d[(int64_t)(ib + 1) * na + ia + 1];
+    return (1.0 - fa) * (1.0 - fb) * v00 + fa * (1.0 - fb) * v10 + (1.0 - fa) * fb * v01 + fa * fb * v11;
+}
+
+__device__ inline double boundary_value(const BoundaryArgs& bc, const double* lo, const double* hi, double G,
+                                        const double e[3])
+{
+    const double x = e[0], y = e[1], z = e[2];
+    switch (bc.kind) {
+    case 1: {  // quadratic c0 + b.x + x^T A x, A from its upper triangle
+        const double* q = bc.quad;
+        return q[0] + q[1] * x + q[2] * y + q[3] * z + q[4] * x * x + 2.0 * q[5] * x * y +
+               2.0 * q[6] * x * z + q[7] * y * y + 2.0 * q[8] * y * z + q[9] * z * z;
+    }
+    case 2: {  // point masses
+        double v = 0.0;
+        for (int j = 0; j < bc.n_items; ++j) {
+            const double* q = bc.items[j];
+            const double dx = x - q[0], dy = y - q[1], dz = z - q[2];
+            v -= G * q[3] / sqrt(dx * dx + dy * dy + dz * dz);
+        }
+        return v;
+    }
+    case 3: {  // homogeneous prisms
+        double v = 0.0;
+        for (int j = 0; j < bc.n_items; ++j) {
+            const double* q = bc.items[j];
+            v += -G * q[6] * prism_newton(q, x, y, z);
+        }
+        return v;
+    }
+    case 4:
+        return face_grid(bc, lo, hi, e);
+    default:
+        return 0.0;
+    }
+}
+
+}  // namespace fk

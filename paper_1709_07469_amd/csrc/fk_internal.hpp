@@ -1,0 +1,192 @@
+// fk_internal.hpp -- launch-argument blocks shared by the host runtime and the
+// kernels of the library.  Everything a walk needs travels by value in the
+// kernel argument block (analytic bodies and coefficient sets included), so a
+// solve reads no host memory after it is enqueued and can be captured in a
+// HIP graph.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "fkgrav.h"
+
+namespace fk {
+
+struct SourceF64 {
+    const float* rho;          // device voxel grid or nullptr
+    int32_t n[3];
+    int32_t has_grid;
+    double origin[3];
+    double spacing[3];
+    double inv[3];             // 1 / spacing
+    int32_t exact[3];          // spacing is a power of two: (x - o) * inv == (x - o) / spacing
+    int32_t n_prisms;
+    int32_t n_spheres;
+    int32_t pad0;
+    double prisms[FK_MAX_PRISMS][7];
+    double spheres[FK_MAX_SPHERES][5];
+};
+
+struct SourceF32 {
+    const float* rho;
+    int32_t n[3];
+    int32_t has_grid;
+    float origin[3];
+    float inv[3];
+    float nf[3];
+    int32_t n_prisms;
+    int32_t n_spheres;
+    int32_t pad0;
+    float prisms[FK_MAX_PRISMS][7];
+    float spheres[FK_MAX_SPHERES][5];
+};
+
+struct BoundaryArgs {
+    int32_t kind;
+    int32_t n_items;
+    double quad[10];
+    double items[FK_MAX_BC_ITEMS][7];
+    const double* face_data;   // device, FACE_GRID only
+    int64_t face_off[6];
+    int32_t face_n[6][2];
+};
+
+// What a walk leaves for the reduction pass: its exit point and its
+// trapezoid sum S = sum_n (rho_n + rho_{n+1}).
+struct ExitRecord {
+    double x, y, z, S;
+};
+
+// Task t of a solve is (station s, local path i, walk w):
+//   t = (s * N + i) * npair + w,  npair = 1 (potential) or 2 (g_z walks +h, -h).
+struct WalkCommon {
+    const double* stations;    // device, n_stations x 3
+    ExitRecord* exits;         // device, n_tasks exit records
+    uint32_t* steps;           // device, n_tasks step counts (bit 31: capped)
+    unsigned long long* queue; // device, next unclaimed task
+    int64_t n_stations;
+    int64_t N;
+    int64_t n_tasks;
+    int64_t path_offset;
+    int64_t max_steps;
+    double lo[3], hi[3];
+    float lo_f[3], hi_f[3];
+    double sdt;                // sqrt(dt)
+    double w;                  // 2 pi G (dt / 2), weight of the trapezoid sum
+    double G;
+    double h;                  // g_z difference step
+    float sdt_f;
+    uint32_t key0, key1;       // Philox key (seed)
+    uint32_t problem_id;
+    int32_t npair;
+    int32_t pairing;
+    int32_t exit_rule;
+    int32_t grab;              // largest queue claim per wavefront
+    uint32_t total_waves;      // resident wavefronts of the launch
+    int32_t pad0;
+    // adjoint replay only: signed trapezoid weights per (station, voxel), and
+    // the forward solve's step counts (walks capped there are skipped)
+    int64_t* counts;
+    const uint32_t* fwd_steps;
+    int64_t nvox;
+};
+
+struct WalkArgsF64 {
+    WalkCommon c;
+    SourceF64 src;
+};
+
+struct WalkArgsF32 {
+    WalkCommon c;
+    SourceF32 src;
+};
+
+// Per-chunk partial statistics of one station: count, mean and sum of
+// squared deviations (Chan et al. merge), and step tallies.
+struct Partial {
+    double n;
+    double mean;
+    double m2;
+    int64_t sum_steps;
+    int64_t max_steps;
+    int64_t n_trunc;
+};
+
+struct ReduceArgs {
+    const ExitRecord* exits;
+    double* values;            // per-walk samples written here
+    const uint32_t* steps;
+    Partial* partials;
+    fk_stat* out;
+    int64_t n_stations;
+    int64_t N;
+    int64_t chunk;             // samples per partial
+    int64_t n_chunks;          // partials per station
+    int32_t npair;
+    int32_t pad0;
+    double two_h;
+    double w;                  // 2 pi G (dt / 2)
+    double G;
+    double lo[3], hi[3];
+    BoundaryArgs bc;
+};
+
+// One problem of a batched solve, as the batch kernels see it (in device
+// memory, written by the descriptor kernels).  Task t of the batch belongs to
+// problem m when task_base[m] <= t < task_base[m+1]; its local task is
+// t - task_base[m], laid out as in WalkCommon.
+struct BatchDesc {
+    WalkCommon c;              // queue unused
+    SourceF64 s64;
+    SourceF32 s32;
+    BoundaryArgs bc;
+    double* values;
+    Partial* partials;
+    fk_stat* out;              // this problem's first station result
+    int64_t n_chunks;
+    int64_t task_base;
+    int64_t block_base;        // first reduction block of this problem
+    int64_t station_base;      // first station of this problem in the batch's station numbering
+};
+
+struct BatchArgs {
+    BatchDesc* desc;           // device, n_problems
+    const int64_t* task_off;   // device, n_problems + 1 prefix sums of tasks
+    const int64_t* block_off;  // device, n_problems + 1 prefix sums of reduction blocks
+    unsigned long long* queue;
+    int64_t n_tasks;
+    int32_t n_problems;
+    int32_t grab;
+    uint32_t total_waves;
+    int32_t precision;
+    int64_t chunk;
+};
+
+struct LaunchCfg {
+    int block;
+    int grid;
+    int grab;
+};
+
+// Host launchers (one translation unit per kernel family).
+hipError_t launch_zero_queue(unsigned long long* queue, hipStream_t stream);
+hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream_t stream, bool adjoint = false);
+hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cfg, hipStream_t stream,
+                           bool adjoint = false);
+// Adjoint helpers: zero the count array; combine counts into the
+// vector-Jacobian product grad_rho[v] = sum_s coef_s * counts[s][v].
+hipError_t launch_fill_zero(int64_t* p, int64_t n, hipStream_t stream);
+hipError_t launch_adjoint_combine(const int64_t* counts, int64_t n_stations, int64_t nvox, const double* grad_out,
+                                  const fk_stat* fwd, double scale, double* grad_rho, hipStream_t stream);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream);
+hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu);
+
+// Batched solve: descriptor upload (by value through kernel arguments, so a
+// captured graph replays it), the persistent walk kernel over all problems,
+// and the batched reduction.
+hipError_t launch_write_words(uint64_t* dst, const uint64_t* host_words, int64_t n_words, hipStream_t stream);
+hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream);
+hipError_t launch_batch_reduce(const BatchArgs& a, int64_t n_blocks, int64_t n_station_threads, hipStream_t stream);
+hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu);
+
+}  // namespace fk

@@ -1,0 +1,179 @@
+// fk_issue_probe.hip -- measures, on the GPU it runs on, the VALU issue cost
+// of the operations one Euler-Maruyama step of the walk kernels is made of:
+// a Philox4x32-10 block, an FP64 and an FP32 Box-Muller pair (uniform bits to
+// two normals), and FP64 / FP32 fused multiply-adds.  Each lane runs 8
+// independent dependency chains whose every result feeds the next input, so
+// nothing folds; the cost is reported in full-rate lane-slots (one slot = one
+// lane-operation at the chip's peak VALU issue rate, CUs x 64 x clock).
+//
+// These costs define the algorithmic work per step used for the walk
+// kernels' ALU roofline.  Build and run: see paper_1709_07469_amd/build.py
+// (target "probe").  Prints one JSON object.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "fk_device.hpp"
+
+#define CHK(x)                                                                              \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess) {                                                             \
+            std::fprintf(stderr, "HIP error %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+            return 1;                                                                       \
+        }                                                                                   \
+    } while (0)
+
+namespace {
+
+constexpr int kChains = 8;
+constexpr int kIter = 512;
+
+__global__ void __launch_bounds__(256) philox_probe(uint32_t* out, uint32_t seed)
+{
+    uint32_t c[kChains][4];
+    for (int j = 0; j < kChains; ++j) {
+        c[j][0] = threadIdx.x + j;
+        c[j][1] = blockIdx.x;
+        c[j][2] = seed;
+        c[j][3] = j;
+    }
+    for (int i = 0; i < kIter; ++i) {
+#pragma unroll
+        for (int j = 0; j < kChains; ++j) {
+            const fk::Block b = fk::philox10(c[j][0], c[j][1], c[j][2], c[j][3], seed, 0x1234u);
+            c[j][0] = b.w0;
+            c[j][1] = b.w1;
+            c[j][2] = b.w2;
+            c[j][3] = b.w3;
+        }
+    }
+    uint32_t s = 0;
+    for (int j = 0; j < kChains; ++j) s ^= c[j][0] ^ c[j][1] ^ c[j][2] ^ c[j][3];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// Box-Muller pairs; the next pair's uniform words are the low bits of the
+// previous normals (2-3 extra integer ops per pair, included in the cost).
+__global__ void __launch_bounds__(256) bm64_probe(uint32_t* out, uint32_t seed)
+{
+    uint32_t w[kChains][4];
+    for (int j = 0; j < kChains; ++j) {
+        w[j][0] = threadIdx.x * 2654435761u + j;
+        w[j][1] = seed ^ blockIdx.x;
+        w[j][2] = w[j][0] * 7u + 3u;
+        w[j][3] = w[j][1] * 5u + 1u;
+    }
+    for (int i = 0; i < kIter / 8; ++i) {
+#pragma unroll
+        for (int j = 0; j < kChains; ++j) {
+            double z0, z1;
+            fk::normals_f64(fk::Block{w[j][0], w[j][1], w[j][2], w[j][3]}, z0, z1);
+            const uint64_t a = (uint64_t)__double_as_longlong(z0), b = (uint64_t)__double_as_longlong(z1);
+            w[j][0] = (uint32_t)a;
+            w[j][1] = (uint32_t)(a >> 32) ^ (uint32_t)b;
+            w[j][2] = (uint32_t)b + w[j][0];
+            w[j][3] = (uint32_t)(b >> 32) ^ w[j][2];
+        }
+    }
+    uint32_t s = 0;
+    for (int j = 0; j < kChains; ++j) s ^= w[j][0] ^ w[j][3];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) bm32_probe(uint32_t* out, uint32_t seed)
+{
+    uint32_t w[kChains][2];
+    for (int j = 0; j < kChains; ++j) {
+        w[j][0] = threadIdx.x * 2654435761u + j;
+        w[j][1] = seed ^ blockIdx.x;
+    }
+    for (int i = 0; i < kIter; ++i) {
+#pragma unroll
+        for (int j = 0; j < kChains; ++j) {
+            float z0, z1;
+            fk::normals_f32(w[j][0], w[j][1], z0, z1);
+            w[j][0] = __float_as_uint(z0) * 2654435761u;
+            w[j][1] = __float_as_uint(z1) ^ w[j][0];
+        }
+    }
+    uint32_t s = 0;
+    for (int j = 0; j < kChains; ++j) s ^= w[j][0] ^ w[j][1];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) fma64_probe(uint32_t* out, uint32_t seed)
+{
+    double a[kChains];
+    for (int j = 0; j < kChains; ++j) a[j] = (double)(seed + threadIdx.x + j);
+    const double m = 0.999999, c = 1e-7;
+    for (int i = 0; i < kIter * 8; ++i) {
+#pragma unroll
+        for (int j = 0; j < kChains; ++j) a[j] = fma(a[j], m, c);
+    }
+    double s = 0.0;
+    for (int j = 0; j < kChains; ++j) s += a[j];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = (uint32_t)s;
+}
+
+__global__ void __launch_bounds__(256) fma32_probe(uint32_t* out, uint32_t seed)
+{
+    float a[kChains];
+    for (int j = 0; j < kChains; ++j) a[j] = (float)(seed + threadIdx.x + j);
+    const float m = 0.999999f, c = 1e-7f;
+    for (int i = 0; i < kIter * 8; ++i) {
+#pragma unroll
+        for (int j = 0; j < kChains; ++j) a[j] = fmaf(a[j], m, c);
+    }
+    float s = 0.0f;
+    for (int j = 0; j < kChains; ++j) s += a[j];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = (uint32_t)s;
+}
+
+typedef void (*Probe)(uint32_t*, uint32_t);
+
+}  // namespace
+
+int main()
+{
+    int dev = 0, cus = 0, khz = 0;
+    CHK(hipGetDevice(&dev));
+    CHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    CHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeClockRate, dev));
+    const int block = 256, grid = cus * 8;
+    uint32_t* buf = nullptr;
+    CHK(hipMalloc(&buf, sizeof(uint32_t) * (size_t)grid * block));
+    struct Item {
+        const char* name;
+        Probe f;
+        double units_per_chain;
+    } items[] = {{"philox_block", philox_probe, (double)kIter},
+                 {"box_muller_pair_f64", bm64_probe, (double)(kIter / 8)},
+                 {"box_muller_pair_f32", bm32_probe, (double)kIter},
+                 {"fma_f64", fma64_probe, (double)(kIter * 8)},
+                 {"fma_f32", fma32_probe, (double)(kIter * 8)}};
+    hipEvent_t e0, e1;
+    CHK(hipEventCreate(&e0));
+    CHK(hipEventCreate(&e1));
+    const double slots_per_s = (double)cus * 64.0 * (double)khz * 1e3;
+    std::printf("{\"cus\": %d, \"clock_mhz\": %.0f, \"lane_slots_per_s\": %.4e", cus, khz / 1e3, slots_per_s);
+    for (const Item& it : items) {
+        hipLaunchKernelGGL(it.f, dim3(grid), dim3(block), 0, 0, buf, 1u);
+        CHK(hipGetLastError());
+        CHK(hipDeviceSynchronize());
+        CHK(hipEventRecord(e0, 0));
+        for (int r = 0; r < 5; ++r) hipLaunchKernelGGL(it.f, dim3(grid), dim3(block), 0, 0, buf, 2u + r);
+        CHK(hipGetLastError());
+        CHK(hipEventRecord(e1, 0));
+        CHK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        CHK(hipEventElapsedTime(&ms, e0, e1));
+        const double units = 5.0 * grid * block * (double)kChains * it.units_per_chain;
+        const double slots = slots_per_s * (ms * 1e-3) / units;
+        std::printf(", \"%s\": {\"ms\": %.3f, \"slots\": %.3f}", it.name, ms, slots);
+    }
+    std::printf("}\n");
+    CHK(hipFree(buf));
+    return 0;
+}

@@ -1,0 +1,194 @@
+"""The C interface without a GPU: the library loads, exports every function
+include/fkgrav.h declares, its struct layouts match the binding's, and every
+argument check rejects bad input on the host before anything is launched."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1709_07469_amd import fkgrav as F
+from paper_1709_07469_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _gpu_present():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+# The argument-check tests hand the library stand-in device addresses that
+# every check must reject before a launch; they run only where no GPU could
+# ever receive such a launch.
+host_only = pytest.mark.skipif(_gpu_present(), reason="passes stand-in device pointers; host-only")
+HEADER = os.path.join(ROOT, "include", "fkgrav.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_functions_are_exported():
+    L = F.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    # every field offset and struct size of the binding against gcc's view of
+    # the header
+    structs = {"fk_box": F.fk_box, "fk_source": F.fk_source, "fk_boundary": F.fk_boundary,
+               "fk_params": F.fk_params, "fk_stat": F.fk_stat, "fk_launch": F.fk_launch,
+               "fk_problem": F.fk_problem}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fkgrav.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        name, field, val = line.split()
+        cls = structs[name]
+        got = C.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert got == int(val), (name, field, got, val)
+        seen += 1
+    assert seen == sum(len(c._fields_) + 1 for c in structs.values())
+
+
+def _host_problem(**over):
+    pr = W.cfg1(100)
+    box = F.fk_box((C.c_double * 3)(*pr.box_lo), (C.c_double * 3)(*pr.box_hi))
+    sp = np.ascontiguousarray(pr.spheres, dtype=np.float64)
+    src = F.fk_source()
+    src.spheres = sp.ctypes.data
+    src.n_spheres = 1
+    bcd = np.ascontiguousarray(pr.bc_data, dtype=np.float64)
+    bc = F.fk_boundary()
+    bc.kind = F.FK_BC_POINT_MASSES
+    bc.data = bcd.ctypes.data
+    bc.n_items = 1
+    prm = F.make_params(pr, **over)
+    return pr, box, src, bc, prm, (sp, bcd)
+
+
+def _call(box, src, bc, prm, n_stations=8, ws_bytes=None, stations=1, out=1, ws=256):
+    L = F.lib()
+    if ws_bytes is None:
+        ws_bytes = L.fk_workspace_bytes(0, n_stations, C.byref(prm)) or 1 << 20
+    return L.fk_solve_potential(C.c_void_p(stations), n_stations, C.byref(box), C.byref(src), C.byref(bc),
+                                C.byref(prm), C.c_void_p(out), C.c_void_p(ws), ws_bytes, None)
+
+
+@host_only
+@pytest.mark.parametrize("field,value,status", [
+    ("dt", 0.0, F.FK_EINVAL), ("dt", float("nan"), F.FK_EINVAL), ("paths_per_station", 1, F.FK_EINVAL),
+    ("precision", 3, F.FK_EINVAL), ("exit_rule", 2, F.FK_EINVAL), ("pairing", 5, F.FK_EINVAL),
+    ("max_steps", 0, F.FK_EINVAL), ("G", float("inf"), F.FK_EINVAL), ("h", -1.0, F.FK_EINVAL),
+    ("path_offset", (1 << 32) - 50, F.FK_EUNSUPPORTED),
+])
+def test_bad_params_rejected(field, value, status):
+    pr, box, src, bc, prm, keep = _host_problem()
+    setattr(prm, field, value)
+    assert _call(box, src, bc, prm, ws_bytes=1 << 30) == status
+    assert F.lib().fk_last_error().decode() != ""
+
+
+@host_only
+def test_bad_box_source_boundary_workspace_rejected():
+    pr, box, src, bc, prm, keep = _host_problem()
+    L = F.lib()
+    box.lo[1] = 2.0
+    assert _call(box, src, bc, prm) == F.FK_EINVAL
+    box.lo[1] = -1.0
+    src.n_spheres = F.FK_MAX_SPHERES + 1
+    assert _call(box, src, bc, prm) == F.FK_EUNSUPPORTED
+    src.n_spheres = 1
+    src.rho = 1024
+    src.n = (C.c_int32 * 3)(4, 0, 4)
+    assert _call(box, src, bc, prm) == F.FK_EINVAL
+    src.n = (C.c_int32 * 3)(4, 4, 4)
+    src.spacing = (C.c_double * 3)(0.1, -0.1, 0.1)
+    assert _call(box, src, bc, prm) == F.FK_EINVAL
+    src.rho = None
+    bc.kind = 9
+    assert _call(box, src, bc, prm) == F.FK_EINVAL
+    bc.kind = F.FK_BC_PRISMS
+    bc.n_items = 0
+    assert _call(box, src, bc, prm) == F.FK_EUNSUPPORTED
+    bc.kind = F.FK_BC_FACE_GRID
+    bc.n_items = 0
+    assert _call(box, src, bc, prm) == F.FK_EINVAL           # face_n all zero
+    bc.kind = F.FK_BC_POINT_MASSES
+    bc.n_items = 1
+    need = L.fk_workspace_bytes(0, 8, C.byref(prm))
+    assert _call(box, src, bc, prm, ws_bytes=need - 1) == F.FK_EWORKSPACE
+    assert _call(box, src, bc, prm, ws=256 + 8) == F.FK_EWORKSPACE   # misaligned
+    assert _call(box, src, bc, prm, out=0) == F.FK_EINVAL
+    assert _call(box, src, bc, prm, stations=0) == F.FK_EINVAL
+    # no stations: nothing to do, nothing launched, no device needed
+    assert _call(box, src, bc, prm, n_stations=0, stations=0, out=0, ws=0) == F.FK_OK
+
+
+def test_station_domain_check():
+    pr, box, src, bc, prm, keep = _host_problem()
+    st = np.array([[0.0, 0.0, 0.5], [0.0, 0.0, 0.99]])
+    F.fk_check_stations(st, box, 0, prm)
+    with pytest.raises(F.FkError) as e:
+        F.fk_check_stations(st, box, 1, prm)           # 0.99 + sqrt(1e-3) leaves the box
+    assert e.value.status == F.FK_EDOMAIN
+    with pytest.raises(F.FkError) as e:
+        F.fk_check_stations(np.array([[0.0, 0.0, 1.0]]), box, 0, prm)
+    assert e.value.status == F.FK_EDOMAIN
+
+
+def test_workspace_layout_and_launch_settings():
+    pr = W.cfg2()
+    prm = F.make_params(pr)
+    v, s, t = F.fk_workspace_layout(0, 64, prm)
+    T = 64 * pr.paths_per_station
+    assert v == 0 and s >= 8 * T and s % 256 == 0 and t >= s + 4 * T + 32 * T
+    v1, s1, t1 = F.fk_workspace_layout(1, 64, prm)
+    assert s1 >= 16 * T and t1 > t
+    assert F.fk_workspace_bytes(0, 64, prm) == t
+    old = F.fk_get_launch(0)
+    F.fk_set_launch(0, 128, 2, 16)
+    assert F.fk_get_launch(0) == {"block": 128, "blocks_per_cu": 2, "grab": 16}
+    with pytest.raises(F.FkError):
+        F.fk_set_launch(0, 96)
+    with pytest.raises(F.FkError):
+        F.fk_set_launch(0, 512)
+    F.fk_set_launch(0, old["block"], old["blocks_per_cu"], old["grab"])
+    assert F.fk_status_string(F.FK_EDOMAIN).startswith("station")
+    assert F.fk_version() >= 100
+
+
+def test_timing_read_without_solves():
+    F.fk_timing_enable(True)
+    assert F.fk_timing_read() == []
+    F.fk_timing_enable(False)
+
+
+def test_product_path_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        F.solve(W.cfg1(10), 0)
