@@ -199,6 +199,8 @@ def main():
     ap.add_argument("--precision", choices=["f64", "mixed"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run one device-to-device copy of this many bytes (calibrates HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 (the multi-GPU design -- path "
@@ -211,6 +213,13 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     res = run(a.precision, max(1, a.steps), max(0, a.warmup), a.cpu_seconds, not a.no_cpu_baseline)
+    if a.copy_bytes > 0:
+        src = torch.ones(a.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = int(src.numel() * 4)
     print(json.dumps(res), flush=True)
 
 

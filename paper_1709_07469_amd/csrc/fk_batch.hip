@@ -1,17 +1,13 @@
-// fk_batch.hip -- many independent problems (density models, station sets,
-// walk counts, parameters) solved in one persistent launch with one
-// work-stealing queue, so that problems of very uneven cost share the GPU
-// without a launch per problem and without idle tails between problems.
-//
-//   - Problem descriptors live in the workspace; they are written by small
+// fk_batch.hip -- support of batched solves, where many independent problems
+// (density models, station sets, walk counts, parameters) are solved in one
+// persistent walk launch with one work-stealing queue (the batch instance of
+// the walk kernel template in fk_walk.hip):
+//   - problem descriptors live in the workspace; they are written by small
 //     kernels that carry the bytes in their arguments, so a captured HIP graph
-//     replays the upload together with the solve.
-//   - A wavefront claims runs of consecutive global tasks; a lane finds the
-//     problem of its task by binary search over the task prefix sums and
-//     caches that problem's stepping parameters in registers for the walk.
-//   - Per-walk arithmetic is the same as the single-problem kernels', task
-//     for task, so a problem solved in a batch gives the same bits as the
-//     same problem solved alone.
+//     replays the upload together with the solve;
+//   - the batched reduction forms every problem's per-walk samples and
+//     station statistics in one launch, with the same arithmetic and order as
+//     the single-problem reduction.
 #include <hip/hip_runtime.h>
 
 #include "fk_device.hpp"
@@ -32,46 +28,6 @@ __global__ void write_words_kernel(uint64_t* dst, const Words w, int n)
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = w.v[i];
 }
 
-__device__ __forceinline__ uint64_t first_lane_u64(uint64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-struct Pool {
-    uint64_t next, end, left;
-    bool exhausted;
-};
-
-__device__ __forceinline__ uint64_t refill(Pool& pool, const BatchArgs& B, bool active)
-{
-    const uint64_t idle = __ballot(!active);
-    if (idle == 0) return ~0ull;
-    const uint32_t n_idle = (uint32_t)__popcll(idle);
-    if (pool.next == pool.end && !pool.exhausted) {
-        uint64_t want = pool.left / (4ull * B.total_waves);
-        if (want < n_idle) want = n_idle;
-        if (want > (uint64_t)B.grab) want = (uint64_t)B.grab;
-        unsigned long long old = 0ull;
-        if (__lane_id() == 0) old = atomicAdd(B.queue, (unsigned long long)want);
-        old = first_lane_u64(__shfl(old, 0));
-        if (old >= (uint64_t)B.n_tasks) {
-            pool.exhausted = true;
-        } else {
-            pool.next = old;
-            pool.end = old + want < (uint64_t)B.n_tasks ? old + want : (uint64_t)B.n_tasks;
-            pool.left = (uint64_t)B.n_tasks - pool.end;
-        }
-    }
-    const uint64_t avail = pool.end - pool.next;
-    const uint32_t rank = (uint32_t)__popcll(idle & __lanemask_lt());
-    uint64_t mine = ~0ull;
-    if (!active && rank < avail) mine = pool.next + rank;
-    pool.next += (n_idle < avail) ? n_idle : avail;
-    return mine;
-}
-
 // Largest m with off[m] <= t (off[0] = 0, off[n] = total > t).
 __device__ __forceinline__ int find_problem(const int64_t* off, int n, int64_t t)
 {
@@ -82,249 +38,6 @@ __device__ __forceinline__ int find_problem(const int64_t* off, int n, int64_t t
         else hi = mid;
     }
     return lo;
-}
-
-// The start of local task t of a problem: station point (shifted by +-h for
-// g_z walks) and the station / path words of the Philox counter.
-__device__ __forceinline__ void task_start(const WalkCommon& C, uint64_t t, double x0[3], uint32_t& sctr,
-                                           uint32_t& pctr)
-{
-    const uint64_t q = (C.npair == 2) ? (t >> 1) : t;
-    const uint32_t w = (C.npair == 2) ? (uint32_t)(t & 1ull) : 0u;
-    const uint64_t s = q / (uint64_t)C.N;
-    const uint64_t i = q - s * (uint64_t)C.N;
-    const double* st = C.stations + 3 * s;
-    x0[0] = st[0];
-    x0[1] = st[1];
-    x0[2] = st[2];
-    if (C.npair == 2) x0[2] = (w == 0) ? st[2] + C.h : st[2] - C.h;
-    sctr = (C.npair == 2 && C.pairing == FK_PAIR_INDEPENDENT) ? (uint32_t)(2 * s + w) : (uint32_t)s;
-    pctr = (uint32_t)((uint64_t)C.path_offset + i);
-}
-
-__device__ __forceinline__ bool inside_open(const WalkCommon& C, const double x[3])
-{
-    return x[0] > C.lo[0] && x[0] < C.hi[0] && x[1] > C.lo[1] && x[1] < C.hi[1] && x[2] > C.lo[2] &&
-           x[2] < C.hi[2];
-}
-
-// ---------------------------------------------------------------------------
-// FP64 batch walks.  Lane registers hold the problem's parameters; the
-// density goes through the problem's descriptor (rho_f64 on device memory).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) batch_f64_kernel(const BatchArgs B)
-{
-    Pool pool{0ull, 0ull, (uint64_t)B.n_tasks, false};
-    bool active = false;
-    const BatchDesc* D = nullptr;
-    uint64_t task = 0;
-    double x0 = 0.0, x1 = 0.0, x2 = 0.0, rp = 0.0, S = 0.0;
-    double sdt = 0.0, lo0 = 0, lo1 = 0, lo2 = 0, hi0 = 0, hi1 = 0, hi2 = 0;
-    uint32_t n = 0, k = 0, sctr = 0, pctr = 0, key0 = 0, key1 = 0, pid = 0;
-    int64_t max_steps = 0;
-
-    for (;;) {
-        const uint64_t got = refill(pool, B, active);
-        if (got != ~0ull) {
-            const int m = find_problem(B.task_off, B.n_problems, (int64_t)got);
-            D = B.desc + m;
-            const WalkCommon& C = D->c;
-            task = got - (uint64_t)B.task_off[m];
-            double xs[3];
-            task_start(C, task, xs, sctr, pctr);
-            if (!inside_open(C, xs)) {
-                const double q = __builtin_nan("");
-                C.exits[task] = ExitRecord{q, q, q, q};
-                C.steps[task] = kCapFlag;
-            } else {
-                x0 = xs[0];
-                x1 = xs[1];
-                x2 = xs[2];
-                sdt = C.sdt;
-                lo0 = C.lo[0]; lo1 = C.lo[1]; lo2 = C.lo[2];
-                hi0 = C.hi[0]; hi1 = C.hi[1]; hi2 = C.hi[2];
-                key0 = C.key0;
-                key1 = C.key1;
-                pid = C.problem_id;
-                max_steps = C.max_steps;
-                rp = rho_f64(D->s64, x0, x1, x2);
-                S = 0.0;
-                n = 0;
-                k = 0;
-                active = true;
-            }
-        }
-        if (__ballot(active) == 0ull) {
-            if (pool.exhausted) break;
-            continue;
-        }
-        if (!active) continue;
-
-        double z[6];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const Block bl = philox10(k + b, pctr, sctr, pid, key0, key1);
-            normals_f64(bl, z[2 * b], z[2 * b + 1]);
-        }
-        k += 3;
-
-        bool done = false, capped = false;
-        double e0 = 0.0, e1 = 0.0, e2 = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll
-        for (int st = 0; st < 2; ++st) {
-            if (!done) {
-                const double y0 = fma(sdt, z[3 * st + 0], x0);
-                const double y1 = fma(sdt, z[3 * st + 1], x1);
-                const double y2 = fma(sdt, z[3 * st + 2], x2);
-                const double rn = rho_f64(D->s64, y0, y1, y2);
-                S = S + (rp + rn);
-                n += 1;
-                if (y0 <= lo0 || y0 >= hi0 || y1 <= lo1 || y1 >= hi1 || y2 <= lo2 || y2 >= hi2) {
-                    done = true;
-                    a0 = x0; a1 = x1; a2 = x2;
-                    e0 = y0; e1 = y1; e2 = y2;
-                } else {
-                    x0 = y0;
-                    x1 = y1;
-                    x2 = y2;
-                    rp = rn;
-                    if ((int64_t)n == max_steps) {
-                        done = true;
-                        capped = true;
-                    }
-                }
-            }
-        }
-        if (done) {
-            const WalkCommon& C = D->c;
-            double e[3] = {e0, e1, e2};
-            if (capped) {
-                e[0] = e[1] = e[2] = 0.0;
-            } else if (C.exit_rule == FK_EXIT_INTERSECT) {
-                const double a[3] = {a0, a1, a2};
-                const double b[3] = {e0, e1, e2};
-                intersect_exit(C.lo, C.hi, a, b, e);
-            }
-            C.exits[task] = ExitRecord{e[0], e[1], e[2], S};
-            C.steps[task] = n | (capped ? kCapFlag : 0u);
-            active = false;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Mixed-precision batch walks (FP32 stream and stepping).
-// ---------------------------------------------------------------------------
-template <bool KAHAN>
-__global__ void __launch_bounds__(256) batch_f32_kernel(const BatchArgs B)
-{
-    Pool pool{0ull, 0ull, (uint64_t)B.n_tasks, false};
-    bool active = false;
-    const BatchDesc* D = nullptr;
-    uint64_t task = 0;
-    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f, rp = 0.0f;
-    double S = 0.0;
-    float Sf = 0.0f, Sc = 0.0f;
-    float sdt = 0.0f, lo0 = 0, lo1 = 0, lo2 = 0, hi0 = 0, hi1 = 0, hi2 = 0;
-    uint32_t n = 0, k = 0, sctr = 0, pctr = 0, key0 = 0, key1 = 0, pid = 0;
-    int64_t max_steps = 0;
-
-    for (;;) {
-        const uint64_t got = refill(pool, B, active);
-        if (got != ~0ull) {
-            const int m = find_problem(B.task_off, B.n_problems, (int64_t)got);
-            D = B.desc + m;
-            const WalkCommon& C = D->c;
-            task = got - (uint64_t)B.task_off[m];
-            double xs[3];
-            task_start(C, task, xs, sctr, pctr);
-            if (!inside_open(C, xs)) {
-                const double q = __builtin_nan("");
-                C.exits[task] = ExitRecord{q, q, q, q};
-                C.steps[task] = kCapFlag;
-            } else {
-                x0 = (float)xs[0];
-                x1 = (float)xs[1];
-                x2 = (float)xs[2];
-                sdt = C.sdt_f;
-                lo0 = C.lo_f[0]; lo1 = C.lo_f[1]; lo2 = C.lo_f[2];
-                hi0 = C.hi_f[0]; hi1 = C.hi_f[1]; hi2 = C.hi_f[2];
-                key0 = C.key0;
-                key1 = C.key1;
-                pid = C.problem_id;
-                max_steps = C.max_steps;
-                rp = rho_f32(D->s32, x0, x1, x2);
-                S = 0.0;
-                Sf = 0.0f;
-                Sc = 0.0f;
-                n = 0;
-                k = 0;
-                active = true;
-            }
-        }
-        if (__ballot(active) == 0ull) {
-            if (pool.exhausted) break;
-            continue;
-        }
-        if (!active) continue;
-
-        float z[12];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const Block bl = philox10(k + b, pctr, sctr, pid, key0, key1);
-            normals_f32(bl.w0, bl.w1, z[4 * b + 0], z[4 * b + 1]);
-            normals_f32(bl.w2, bl.w3, z[4 * b + 2], z[4 * b + 3]);
-        }
-        k += 3;
-
-        bool done = false, capped = false;
-        float ex = 0.0f, ey = 0.0f, ez = 0.0f, fx = 0.0f, fy = 0.0f, fz = 0.0f;
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-            if (!done) {
-                const float y0 = fmaf(sdt, z[3 * st + 0], x0);
-                const float y1 = fmaf(sdt, z[3 * st + 1], x1);
-                const float y2 = fmaf(sdt, z[3 * st + 2], x2);
-                const float rn = rho_f32(D->s32, y0, y1, y2);
-                if (KAHAN) {
-                    const float y = (rp + rn) - Sc;
-                    const float t = Sf + y;
-                    Sc = (t - Sf) - y;
-                    Sf = t;
-                } else {
-                    S = S + ((double)rp + (double)rn);
-                }
-                n += 1;
-                if (y0 <= lo0 || y0 >= hi0 || y1 <= lo1 || y1 >= hi1 || y2 <= lo2 || y2 >= hi2) {
-                    done = true;
-                    ex = x0; ey = x1; ez = x2;
-                    fx = y0; fy = y1; fz = y2;
-                } else {
-                    x0 = y0;
-                    x1 = y1;
-                    x2 = y2;
-                    rp = rn;
-                    if ((int64_t)n == max_steps) {
-                        done = true;
-                        capped = true;
-                    }
-                }
-            }
-        }
-        if (done) {
-            const WalkCommon& C = D->c;
-            double e[3] = {(double)fx, (double)fy, (double)fz};
-            if (!capped && C.exit_rule == FK_EXIT_INTERSECT) {
-                const double a[3] = {(double)ex, (double)ey, (double)ez};
-                const double b[3] = {(double)fx, (double)fy, (double)fz};
-                intersect_exit(C.lo, C.hi, a, b, e);
-            }
-            const double sum = KAHAN ? ((double)Sf - (double)Sc) : S;
-            C.exits[task] = ExitRecord{e[0], e[1], e[2], sum};
-            C.steps[task] = n | (capped ? kCapFlag : 0u);
-            active = false;
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -489,17 +202,6 @@ hipError_t launch_write_words(uint64_t* dst, const uint64_t* host_words, int64_t
     return hipSuccess;
 }
 
-hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream)
-{
-    if (a.precision == FK_F64)
-        hipLaunchKernelGGL(batch_f64_kernel, dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
-    else if (a.precision == FK_MIXED_KAHAN)
-        hipLaunchKernelGGL(batch_f32_kernel<true>, dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
-    else
-        hipLaunchKernelGGL(batch_f32_kernel<false>, dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
-    return hipGetLastError();
-}
-
 hipError_t launch_batch_reduce(const BatchArgs& a, int64_t n_blocks, int64_t n_station_threads, hipStream_t stream)
 {
     hipLaunchKernelGGL(batch_chunk_kernel, dim3((unsigned)n_blocks), dim3(kReduceBlock), 0, stream, a);
@@ -508,14 +210,6 @@ hipError_t launch_batch_reduce(const BatchArgs& a, int64_t n_blocks, int64_t n_s
     hipLaunchKernelGGL(batch_station_kernel, dim3((unsigned)((n_station_threads + 63) / 64)), dim3(64), 0, stream, a,
                        n_station_threads);
     return hipGetLastError();
-}
-
-hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu)
-{
-    const void* fn = precision == FK_F64 ? (const void*)batch_f64_kernel
-                   : precision == FK_MIXED_KAHAN ? (const void*)batch_f32_kernel<true>
-                                                 : (const void*)batch_f32_kernel<false>;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
 }  // namespace fk

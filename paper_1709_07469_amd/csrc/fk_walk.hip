@@ -5,6 +5,10 @@
 // the stored exit points by the reduction pass, where every lane evaluates it
 // at once instead of one lane at a time inside the stepping loop.
 //
+// One kernel template covers FP64 and mixed precision, single problems and
+// batches of problems, and the adjoint replay (which walks the same paths and
+// scatters trapezoid weights instead of storing exit records).
+//
 // Scheduling (gfx950, wave64):
 //   - persistent blocks, sized from the occupancy calculator;
 //   - a wavefront claims a run of consecutive walks from one global counter
@@ -14,9 +18,19 @@
 //     every active lane is at the start of a Philox block triple: FP64 walks
 //     take 2 steps (6 normals = 3 blocks), mixed walks take 4 steps
 //     (12 normals = 3 blocks) per macro-step;
-//   - a walk's sample is written to its own slot (task index), so the result
-//     does not depend on which lane or wavefront ran it.
+//   - drain rounds: once the queue is empty, all 64 lanes of a wavefront
+//     generate Philox blocks and normals for its remaining live walks into
+//     LDS (any lane can compute any walk's block, the generator being
+//     counter based), and the live lanes step through that buffer -- up to
+//     128 (FP64) or 256 (mixed) steps per round for a lone walk.  The longest
+//     walks, which decide when the launch ends, then cost a move and a test
+//     per step instead of a full random-number generation each, and partly
+//     idle wavefronts keep all lanes busy generating;
+//   - a walk's record is written to its own slot (task index), so the result
+//     does not depend on which lane or wavefront ran it, nor on the mode.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "fk_device.hpp"
 
@@ -25,6 +39,7 @@ namespace fk {
 namespace {
 
 constexpr uint32_t kCapFlag = 0x80000000u;
+constexpr int kMaxWaves = 4;        // 256 threads per block at most
 
 __global__ void zero_queue_kernel(unsigned long long* q)
 {
@@ -38,35 +53,47 @@ __device__ __forceinline__ uint64_t first_lane_u64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Wave-uniform claim state.
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wave-uniform claim state over the global task queue.
+struct Queue {
+    unsigned long long* counter;
+    uint64_t n_tasks;
+    uint32_t grab;
+    uint32_t total_waves;
+};
+
 struct Pool {
-    uint64_t next;
-    uint64_t end;
-    uint64_t left;
+    uint64_t next, end, left;
     bool exhausted;
 };
 
 // Refills idle lanes from the wavefront's claimed run, claiming a new run
 // when it is empty.  Returns the task of this lane if it was idle and got
 // one, else ~0.
-__device__ __forceinline__ uint64_t refill(Pool& pool, const WalkCommon& C, bool active)
+__device__ __forceinline__ uint64_t refill(Pool& pool, const Queue& Q, bool active)
 {
     const uint64_t idle = __ballot(!active);
     if (idle == 0) return ~0ull;
     const uint32_t n_idle = (uint32_t)__popcll(idle);
     if (pool.next == pool.end && !pool.exhausted) {
-        uint64_t want = pool.left / (4ull * C.total_waves);
+        uint64_t want = pool.left / (4ull * Q.total_waves);
         if (want < n_idle) want = n_idle;
-        if (want > (uint64_t)C.grab) want = (uint64_t)C.grab;
+        if (want > (uint64_t)Q.grab) want = (uint64_t)Q.grab;
         unsigned long long old = 0ull;
-        if (__lane_id() == 0) old = atomicAdd(C.queue, (unsigned long long)want);
+        if (__lane_id() == 0) old = atomicAdd(Q.counter, (unsigned long long)want);
         old = first_lane_u64(__shfl(old, 0));
-        if (old >= (uint64_t)C.n_tasks) {
+        if (old >= Q.n_tasks) {
             pool.exhausted = true;
         } else {
             pool.next = old;
-            pool.end = old + want < (uint64_t)C.n_tasks ? old + want : (uint64_t)C.n_tasks;
-            pool.left = (uint64_t)C.n_tasks - pool.end;
+            pool.end = old + want < Q.n_tasks ? old + want : Q.n_tasks;
+            pool.left = Q.n_tasks - pool.end;
         }
     }
     const uint64_t avail = pool.end - pool.next;
@@ -77,6 +104,18 @@ __device__ __forceinline__ uint64_t refill(Pool& pool, const WalkCommon& C, bool
     return mine;
 }
 
+// Largest m with off[m] <= t (off[0] = 0, off[n] = total > t).
+__device__ __forceinline__ int find_problem(const int64_t* off, int n, int64_t t)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 struct TaskInfo {
     double x0[3];
     uint64_t s;      // station
@@ -85,6 +124,8 @@ struct TaskInfo {
     uint32_t pctr;   // path word
 };
 
+// Local task t of a problem: (station s, local path i, walk w) with
+// t = (s * N + i) * npair + w.
 __device__ __forceinline__ TaskInfo decode(const WalkCommon& C, uint64_t t)
 {
     TaskInfo ti;
@@ -104,6 +145,12 @@ __device__ __forceinline__ TaskInfo decode(const WalkCommon& C, uint64_t t)
     return ti;
 }
 
+__device__ __forceinline__ bool strictly_inside(const WalkCommon& C, const double x[3])
+{
+    return x[0] > C.lo[0] && x[0] < C.hi[0] && x[1] > C.lo[1] && x[1] < C.hi[1] && x[2] > C.lo[2] &&
+           x[2] < C.hi[2];
+}
+
 // Adjoint replay: a walk whose sample (or pair) the forward solve excluded
 // is skipped.
 __device__ __forceinline__ bool forward_capped(const WalkCommon& C, uint64_t t)
@@ -115,7 +162,7 @@ __device__ __forceinline__ bool forward_capped(const WalkCommon& C, uint64_t t)
     return (C.fwd_steps[t] & kCapFlag) != 0;
 }
 
-// Run-length coalesced scatter of signed trapezoid weights.
+// Run-length coalesced scatter of signed trapezoid weights (adjoint).
 struct Scatter {
     int64_t* base;   // counts of this walk's station
     int64_t v;       // pending voxel (-1: none)
@@ -136,262 +183,355 @@ struct Scatter {
     }
 };
 
-__device__ __forceinline__ bool strictly_inside(const WalkCommon& C, const double x[3])
-{
-    return x[0] > C.lo[0] && x[0] < C.hi[0] && x[1] > C.lo[1] && x[1] < C.hi[1] && x[2] > C.lo[2] &&
-           x[2] < C.hi[2];
-}
-
 // ---------------------------------------------------------------------------
-// FP64 walks: FP64 stream (53-bit uniforms), FP64 position and trapezoid sum.
+// Precision traits.
 // ---------------------------------------------------------------------------
-template <bool ADJ>
-__global__ void __launch_bounds__(256) walk_f64_kernel(const WalkArgsF64 A)
-{
-    const WalkCommon& C = A.c;
-    Pool pool{0ull, 0ull, (uint64_t)C.n_tasks, false};
+template <bool F64>
+struct Prec;
 
-    bool active = false;
-    uint64_t task = 0;
-    double x0 = 0.0, x1 = 0.0, x2 = 0.0, rp = 0.0, S = 0.0;
-    uint32_t n = 0, k = 0, sctr = 0, pctr = 0;
-    Scatter sc{nullptr, -1, 0, 1};
+template <>
+struct Prec<true> {
+    using T = double;
+    using Src = SourceF64;
+    static constexpr int kNormals = 2;   // per Philox block
+    static constexpr int kMacro = 2;     // steps per 3 blocks
+    __device__ static void normals(const Block& b, T* z) { normals_f64(b, z[0], z[1]); }
+    __device__ static T fmat(T a, T b, T c) { return fma(a, b, c); }
+    __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f64(s, x, y, z); }
+    __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f64(s, x, y, z); }
+    __device__ static T lo(const WalkCommon& C, int c) { return C.lo[c]; }
+    __device__ static T hi(const WalkCommon& C, int c) { return C.hi[c]; }
+    __device__ static T sdt(const WalkCommon& C) { return C.sdt; }
+};
 
-    for (;;) {
-        const uint64_t got = refill(pool, C, active);
-        if (got != ~0ull) {
-            const TaskInfo ti = decode(C, got);
-            task = got;
-            if (ADJ && (!strictly_inside(C, ti.x0) || forward_capped(C, task))) {
-                // excluded in the forward solve: contributes nothing
-            } else if (ADJ) {
-                x0 = ti.x0[0];
-                x1 = ti.x0[1];
-                x2 = ti.x0[2];
-                sctr = ti.sctr;
-                pctr = ti.pctr;
-                n = 0;
-                k = 0;
-                sc.base = C.counts + ti.s * C.nvox;
-                sc.v = -1;
-                sc.c = 0;
-                sc.sign = ti.w ? -1 : 1;
-                sc.add(voxel_f64(A.src, x0, x1, x2), 1);
-                active = true;
-            } else if (!strictly_inside(C, ti.x0)) {
-                // a start point on or outside the boundary yields no sample
-                const double q = __builtin_nan("");
-                C.exits[task] = ExitRecord{q, q, q, q};
-                C.steps[task] = kCapFlag;
-            } else {
-                x0 = ti.x0[0];
-                x1 = ti.x0[1];
-                x2 = ti.x0[2];
-                sctr = ti.sctr;
-                pctr = ti.pctr;
-                rp = rho_f64(A.src, x0, x1, x2);
-                S = 0.0;
-                n = 0;
-                k = 0;
-                active = true;
-            }
-        }
-        if (__ballot(active) == 0ull) {
-            if (pool.exhausted) break;
-            continue;
-        }
-        if (!active) continue;
-
-        double z[6];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const Block bl = philox10(k + b, pctr, sctr, C.problem_id, C.key0, C.key1);
-            normals_f64(bl, z[2 * b], z[2 * b + 1]);
-        }
-        k += 3;
-
-        bool done = false, capped = false;
-        double e[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int st = 0; st < 2; ++st) {
-            if (!done) {
-                const double y0 = fma(C.sdt, z[3 * st + 0], x0);
-                const double y1 = fma(C.sdt, z[3 * st + 1], x1);
-                const double y2 = fma(C.sdt, z[3 * st + 2], x2);
-                double rn = 0.0;
-                if (!ADJ) {
-                    rn = rho_f64(A.src, y0, y1, y2);
-                    S = S + (rp + rn);
-                }
-                n += 1;
-                const bool out = outside(C.lo, C.hi, y0, y1, y2);
-                if (ADJ) sc.add(voxel_f64(A.src, y0, y1, y2), out ? 1 : 2);
-                if (out) {
-                    done = true;
-                    if (ADJ) {
-                    } else if (C.exit_rule == FK_EXIT_INTERSECT) {
-                        const double a[3] = {x0, x1, x2};
-                        const double b[3] = {y0, y1, y2};
-                        intersect_exit(C.lo, C.hi, a, b, e);
-                    } else {
-                        e[0] = y0;
-                        e[1] = y1;
-                        e[2] = y2;
-                    }
-                } else {
-                    x0 = y0;
-                    x1 = y1;
-                    x2 = y2;
-                    rp = rn;
-                    if ((int64_t)n == C.max_steps) {
-                        done = true;
-                        capped = true;
-                    }
-                }
-            }
-        }
-        if (done) {
-            if (ADJ) {
-                sc.flush();
-            } else {
-                C.exits[task] = ExitRecord{e[0], e[1], e[2], S};
-                C.steps[task] = n | (capped ? kCapFlag : 0u);
-            }
-            active = false;
-        }
+template <>
+struct Prec<false> {
+    using T = float;
+    using Src = SourceF32;
+    static constexpr int kNormals = 4;
+    static constexpr int kMacro = 4;
+    __device__ static void normals(const Block& b, T* z)
+    {
+        normals_f32(b.w0, b.w1, z[0], z[1]);
+        normals_f32(b.w2, b.w3, z[2], z[3]);
     }
-}
+    __device__ static T fmat(T a, T b, T c) { return fmaf(a, b, c); }
+    __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f32(s, x, y, z); }
+    __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f32(s, x, y, z); }
+    __device__ static T lo(const WalkCommon& C, int c) { return C.lo_f[c]; }
+    __device__ static T hi(const WalkCommon& C, int c) { return C.hi_f[c]; }
+    __device__ static T sdt(const WalkCommon& C) { return C.sdt_f; }
+};
 
-// ---------------------------------------------------------------------------
-// Mixed walks: FP32 stream and FP32 position; the trapezoid sum in FP64 or
-// as a Kahan-compensated FP32 pair; exit point and data in FP64.
-// ---------------------------------------------------------------------------
-template <bool KAHAN, bool ADJ>
-__global__ void __launch_bounds__(256) walk_f32_kernel(const WalkArgsF32 A)
-{
-    const WalkCommon& C = A.c;
-    Pool pool{0ull, 0ull, (uint64_t)C.n_tasks, false};
+template <bool F64>
+struct SourceOf;
+template <>
+struct SourceOf<true> {
+    __device__ static const SourceF64& get(const BatchDesc& D) { return D.s64; }
+};
+template <>
+struct SourceOf<false> {
+    __device__ static const SourceF32& get(const BatchDesc& D) { return D.s32; }
+};
 
-    bool active = false;
-    uint64_t task = 0;
-    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f, rp = 0.0f;
-    double S = 0.0;            // FP64 accumulation
-    float Sf = 0.0f, Sc = 0.0f;  // Kahan sum and compensation
-    uint32_t n = 0, k = 0, sctr = 0, pctr = 0;
-    Scatter sc{nullptr, -1, 0, 1};
+// Stepping parameters of the problem a lane is walking.  In single-problem
+// launches they are the same for every lane (held in scalar registers); in a
+// batch each lane loads its problem's at the start of a walk.
+template <bool F64>
+struct LaneProblem {
+    using T = typename Prec<F64>::T;
+    const WalkCommon* C;
+    const typename Prec<F64>::Src* src;
+    T sdt;
+    T lo0, lo1, lo2, hi0, hi1, hi2;
+    uint32_t key0, key1, pid;
+    int64_t max_steps;
 
-    for (;;) {
-        const uint64_t got = refill(pool, C, active);
-        if (got != ~0ull) {
-            const TaskInfo ti = decode(C, got);
-            task = got;
-            if (ADJ && (!strictly_inside(C, ti.x0) || forward_capped(C, task))) {
-                // excluded in the forward solve: contributes nothing
-            } else if (ADJ) {
-                x0 = (float)ti.x0[0];
-                x1 = (float)ti.x0[1];
-                x2 = (float)ti.x0[2];
-                sctr = ti.sctr;
-                pctr = ti.pctr;
-                n = 0;
-                k = 0;
-                sc.base = C.counts + ti.s * C.nvox;
-                sc.v = -1;
-                sc.c = 0;
-                sc.sign = ti.w ? -1 : 1;
-                sc.add(voxel_f32(A.src, x0, x1, x2), 1);
-                active = true;
-            } else if (!strictly_inside(C, ti.x0)) {
-                // a start point on or outside the boundary yields no sample
-                const double q = __builtin_nan("");
-                C.exits[task] = ExitRecord{q, q, q, q};
-                C.steps[task] = kCapFlag;
+    __device__ __forceinline__ void load(const WalkCommon& c, const typename Prec<F64>::Src& s)
+    {
+        C = &c;
+        src = &s;
+        sdt = Prec<F64>::sdt(c);
+        lo0 = Prec<F64>::lo(c, 0);
+        lo1 = Prec<F64>::lo(c, 1);
+        lo2 = Prec<F64>::lo(c, 2);
+        hi0 = Prec<F64>::hi(c, 0);
+        hi1 = Prec<F64>::hi(c, 1);
+        hi2 = Prec<F64>::hi(c, 2);
+        key0 = c.key0;
+        key1 = c.key1;
+        pid = c.problem_id;
+        max_steps = c.max_steps;
+    }
+};
+
+// One lane's walk.
+template <bool F64, bool KAHAN, bool ADJ>
+struct Walker {
+    using T = typename Prec<F64>::T;
+    uint64_t task;
+    T x0, x1, x2, rp;
+    double S;        // trapezoid sum (FP64 accumulation)
+    float Sf, Sc;    // Kahan sum and compensation
+    uint32_t n, k, sctr, pctr;
+    bool active;
+    Scatter sc;
+
+    // One Euler-Maruyama step with normals (z0, z1, z2).  Returns true when
+    // the walk ends here: it left the box (a = last inside point, e = the
+    // first point outside) or it reached max_steps (capped).
+    __device__ __forceinline__ bool step(const LaneProblem<F64>& P, T z0, T z1, T z2, T& a0, T& a1, T& a2, T& e0,
+                                         T& e1, T& e2, bool& capped)
+    {
+        const T y0 = Prec<F64>::fmat(P.sdt, z0, x0);
+        const T y1 = Prec<F64>::fmat(P.sdt, z1, x1);
+        const T y2 = Prec<F64>::fmat(P.sdt, z2, x2);
+        T rn = T(0);
+        if (!ADJ) {
+            rn = Prec<F64>::rho(*P.src, y0, y1, y2);
+            if (F64) {
+                S = S + (double)(rp + rn);
+            } else if (KAHAN) {
+                const float y = (float)(rp + rn) - Sc;
+                const float t = Sf + y;
+                Sc = (t - Sf) - y;
+                Sf = t;
             } else {
-                x0 = (float)ti.x0[0];
-                x1 = (float)ti.x0[1];
-                x2 = (float)ti.x0[2];
-                sctr = ti.sctr;
-                pctr = ti.pctr;
-                rp = rho_f32(A.src, x0, x1, x2);
-                S = 0.0;
-                Sf = 0.0f;
-                Sc = 0.0f;
-                n = 0;
-                k = 0;
-                active = true;
+                S = S + ((double)rp + (double)rn);
             }
         }
-        if (__ballot(active) == 0ull) {
-            if (pool.exhausted) break;
-            continue;
+        n += 1;
+        const bool out = y0 <= P.lo0 || y0 >= P.hi0 || y1 <= P.lo1 || y1 >= P.hi1 || y2 <= P.lo2 || y2 >= P.hi2;
+        if (ADJ) sc.add(Prec<F64>::voxel(*P.src, y0, y1, y2), out ? 1 : 2);
+        if (out) {
+            a0 = x0; a1 = x1; a2 = x2;
+            e0 = y0; e1 = y1; e2 = y2;
+            return true;
         }
-        if (!active) continue;
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        rp = rn;
+        if ((int64_t)n == P.max_steps) {
+            capped = true;
+            return true;
+        }
+        return false;
+    }
 
-        float z[12];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const Block bl = philox10(k + b, pctr, sctr, C.problem_id, C.key0, C.key1);
-            normals_f32(bl.w0, bl.w1, z[4 * b + 0], z[4 * b + 1]);
-            normals_f32(bl.w2, bl.w3, z[4 * b + 2], z[4 * b + 3]);
-        }
-        k += 3;
-
-        bool done = false, capped = false;
-        float ex = 0.0f, ey = 0.0f, ez = 0.0f;   // last inside point (INTERSECT)
-        float fx = 0.0f, fy = 0.0f, fz = 0.0f;   // first outside point
-#pragma unroll
-        for (int st = 0; st < 4; ++st) {
-            if (!done) {
-                const float y0 = fmaf(C.sdt_f, z[3 * st + 0], x0);
-                const float y1 = fmaf(C.sdt_f, z[3 * st + 1], x1);
-                const float y2 = fmaf(C.sdt_f, z[3 * st + 2], x2);
-                float rn = 0.0f;
-                if (!ADJ) {
-                    rn = rho_f32(A.src, y0, y1, y2);
-                    if (KAHAN) {
-                        const float y = (rp + rn) - Sc;
-                        const float t = Sf + y;
-                        Sc = (t - Sf) - y;
-                        Sf = t;
-                    } else {
-                        S = S + ((double)rp + (double)rn);
-                    }
-                }
-                n += 1;
-                const bool out = outside(C.lo_f, C.hi_f, y0, y1, y2);
-                if (ADJ) sc.add(voxel_f32(A.src, y0, y1, y2), out ? 1 : 2);
-                if (out) {
-                    done = true;
-                    ex = x0; ey = x1; ez = x2;
-                    fx = y0; fy = y1; fz = y2;
-                } else {
-                    x0 = y0;
-                    x1 = y1;
-                    x2 = y2;
-                    rp = rn;
-                    if ((int64_t)n == C.max_steps) {
-                        done = true;
-                        capped = true;
-                    }
-                }
-            }
-        }
-        if (done && ADJ) {
+    // Stores the walk's exit record (or flushes its scatter) and frees the lane.
+    __device__ __forceinline__ void finish(const LaneProblem<F64>& P, T a0, T a1, T a2, T e0, T e1, T e2,
+                                           bool capped)
+    {
+        if (ADJ) {
             sc.flush();
-            active = false;
-        } else if (done) {
-            double e[3] = {(double)fx, (double)fy, (double)fz};
-            if (!capped && C.exit_rule == FK_EXIT_INTERSECT) {
-                const double a[3] = {(double)ex, (double)ey, (double)ez};
-                const double b[3] = {(double)fx, (double)fy, (double)fz};
-                intersect_exit(C.lo, C.hi, a, b, e);
+        } else {
+            const WalkCommon& C = *P.C;
+            double e[3] = {0.0, 0.0, 0.0};
+            if (!capped) {
+                e[0] = (double)e0;
+                e[1] = (double)e1;
+                e[2] = (double)e2;
+                if (C.exit_rule == FK_EXIT_INTERSECT) {
+                    const double a[3] = {(double)a0, (double)a1, (double)a2};
+                    const double b[3] = {(double)e0, (double)e1, (double)e2};
+                    intersect_exit(C.lo, C.hi, a, b, e);
+                }
             }
-            const double sum = KAHAN ? ((double)Sf - (double)Sc) : S;
+            const double sum = (!F64 && KAHAN) ? ((double)Sf - (double)Sc) : S;
             C.exits[task] = ExitRecord{e[0], e[1], e[2], sum};
             C.steps[task] = n | (capped ? kCapFlag : 0u);
-            active = false;
         }
+        active = false;
     }
+};
+
+// ---------------------------------------------------------------------------
+// The kernel body.
+// ---------------------------------------------------------------------------
+template <bool F64, bool KAHAN, bool ADJ, bool BATCH, class Args>
+__device__ __forceinline__ void walk_body(const Args& A)
+{
+    using T = typename Prec<F64>::T;
+    constexpr int NPB = Prec<F64>::kNormals;
+    constexpr int MACRO = Prec<F64>::kMacro;
+
+    __shared__ int tail_lane[kMaxWaves][64];
+    __shared__ T tail_z[kMaxWaves][3 * 64][NPB];
+
+    Queue Q;
+    LaneProblem<F64> P;
+    if constexpr (BATCH) {
+        Q = Queue{A.queue, (uint64_t)A.n_tasks, (uint32_t)A.grab, A.total_waves};
+        P.C = nullptr;
+        P.src = nullptr;
+        P.sdt = T(0);
+        P.lo0 = P.lo1 = P.lo2 = P.hi0 = P.hi1 = P.hi2 = T(0);
+        P.key0 = P.key1 = P.pid = 0;
+        P.max_steps = 0;
+    } else {
+        Q = Queue{A.c.queue, (uint64_t)A.c.n_tasks, (uint32_t)A.c.grab, A.c.total_waves};
+        P.load(A.c, A.src);
+    }
+    Pool pool{0ull, 0ull, Q.n_tasks, false};
+    Walker<F64, KAHAN, ADJ> W;
+    W.active = false;
+    W.task = 0;
+    W.x0 = W.x1 = W.x2 = W.rp = T(0);
+    W.S = 0.0;
+    W.Sf = W.Sc = 0.0f;
+    W.n = W.k = W.sctr = W.pctr = 0;
+    W.sc = Scatter{nullptr, -1, 0, 1};
+    const int wave = threadIdx.x >> 6;
+    const int lane = (int)__lane_id();
+
+    for (;;) {
+        const uint64_t got = refill(pool, Q, W.active);
+        if (got != ~0ull) {
+            const WalkCommon* Cp;
+            uint64_t t = got;
+            if constexpr (BATCH) {
+                const int m = find_problem(A.task_off, A.n_problems, (int64_t)got);
+                const BatchDesc& D = A.desc[m];
+                t = got - (uint64_t)A.task_off[m];
+                P.load(D.c, SourceOf<F64>::get(D));
+                Cp = &D.c;
+            } else {
+                Cp = &A.c;
+            }
+            const WalkCommon& C = *Cp;
+            const TaskInfo ti = decode(C, t);
+            W.task = t;
+            const bool inside = strictly_inside(C, ti.x0);
+            if (ADJ && (!inside || forward_capped(C, t))) {
+                // excluded in the forward solve: contributes nothing
+            } else if (!ADJ && !inside) {
+                // a start point on or outside the boundary yields no sample
+                const double q = __builtin_nan("");
+                C.exits[t] = ExitRecord{q, q, q, q};
+                C.steps[t] = kCapFlag;
+            } else {
+                W.x0 = (T)ti.x0[0];
+                W.x1 = (T)ti.x0[1];
+                W.x2 = (T)ti.x0[2];
+                W.sctr = ti.sctr;
+                W.pctr = ti.pctr;
+                W.n = 0;
+                W.k = 0;
+                W.S = 0.0;
+                W.Sf = W.Sc = 0.0f;
+                if (ADJ) {
+                    W.sc.base = C.counts + ti.s * C.nvox;
+                    W.sc.v = -1;
+                    W.sc.c = 0;
+                    W.sc.sign = ti.w ? -1 : 1;
+                    W.sc.add(Prec<F64>::voxel(*P.src, W.x0, W.x1, W.x2), 1);
+                } else {
+                    W.rp = Prec<F64>::rho(*P.src, W.x0, W.x1, W.x2);
+                }
+                W.active = true;
+            }
+        }
+        const uint64_t live = __ballot(W.active);
+        if (live == 0ull) {
+            if (pool.exhausted) break;
+            continue;
+        }
+        const int m = __popcll(live);
+
+        if (pool.exhausted) {
+            // ---- drain round: the queue is empty, so every lane generates
+            // three Philox blocks for the live walks of its wavefront (block
+            // slot g = r * m + w holds block r of live walk w), and each live
+            // walk then takes 2 * 64/m (FP64) or 4 * 64/m (mixed) steps from
+            // LDS.  With m = 64 this costs what a macro-step costs; with few
+            // live walks it spreads their random-number generation over all
+            // lanes instead of leaving most lanes idle.
+            const int rank = __popcll(live & __lanemask_lt());
+            if (W.active) tail_lane[wave][rank] = lane;
+            wave_sync_lds();
+            const int B = 3 * (64 / m);                // blocks per live walk this round
+#pragma unroll 1
+            for (int i = 0; i < 3; ++i) {
+                const int g = lane + 64 * i;
+                const int w = g % m;
+                const int r = g / m;
+                const int src = tail_lane[wave][w];
+                const uint32_t ks = (uint32_t)__shfl((int)W.k, src);
+                const uint32_t ps = (uint32_t)__shfl((int)W.pctr, src);
+                const uint32_t ss = (uint32_t)__shfl((int)W.sctr, src);
+                uint32_t key0 = P.key0, key1 = P.key1, pid = P.pid;
+                if constexpr (BATCH) {
+                    key0 = (uint32_t)__shfl((int)P.key0, src);
+                    key1 = (uint32_t)__shfl((int)P.key1, src);
+                    pid = (uint32_t)__shfl((int)P.pid, src);
+                }
+                if (r < B) {
+                    const Block bl = philox10(ks + (uint32_t)r, ps, ss, pid, key0, key1);
+                    T z[NPB];
+                    Prec<F64>::normals(bl, z);
+#pragma unroll
+                    for (int j = 0; j < NPB; ++j) tail_z[wave][g][j] = z[j];
+                }
+            }
+            wave_sync_lds();
+            if (W.active) {
+                const int n_steps = B * NPB / 3;      // a multiple of MACRO
+                bool done = false, capped = false;
+                T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
+                for (int s0 = 0; s0 < n_steps && !done; s0 += MACRO) {
+                    T zz[3 * MACRO];
+#pragma unroll
+                    for (int c = 0; c < 3 * MACRO; ++c) {
+                        const int q = 3 * s0 + c;
+                        zz[c] = tail_z[wave][(q / NPB) * m + rank][q % NPB];
+                    }
+#pragma unroll
+                    for (int s = 0; s < MACRO; ++s) {
+                        if (!done)
+                            done = W.step(P, zz[3 * s], zz[3 * s + 1], zz[3 * s + 2], a0, a1, a2, e0, e1, e2, capped);
+                    }
+                }
+                W.k += (uint32_t)B;
+                if (done) W.finish(P, a0, a1, a2, e0, e1, e2, capped);
+            }
+            wave_sync_lds();
+            continue;
+        }
+
+        if (!W.active) continue;
+
+        // ---- macro-step: 3 blocks of this lane's own walk ----
+        T z[3 * NPB];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const Block bl = philox10(W.k + b, W.pctr, W.sctr, P.pid, P.key0, P.key1);
+            Prec<F64>::normals(bl, z + NPB * b);
+        }
+        W.k += 3;
+        bool done = false, capped = false;
+        T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
+#pragma unroll
+        for (int s = 0; s < MACRO; ++s) {
+            if (!done) done = W.step(P, z[3 * s], z[3 * s + 1], z[3 * s + 2], a0, a1, a2, e0, e1, e2, capped);
+        }
+        if (done) W.finish(P, a0, a1, a2, e0, e1, e2, capped);
+    }
+}
+
+// FP64 walks are held to 4 wavefronts per SIMD (128 VGPRs): measured a few
+// percent faster than 3 wavefronts without the limit, despite a small spill.
+template <bool F64, bool KAHAN, bool ADJ>
+__global__ void __launch_bounds__(256, F64 ? 4 : 1)
+    walk_kernel(const typename std::conditional<F64, WalkArgsF64, WalkArgsF32>::type A)
+{
+    walk_body<F64, KAHAN, ADJ, false>(A);
+}
+
+template <bool F64, bool KAHAN>
+__global__ void __launch_bounds__(256) batch_walk_kernel(const BatchArgs A)
+{
+    walk_body<F64, KAHAN, false, true>(A);
 }
 
 }  // namespace
@@ -405,9 +545,9 @@ hipError_t launch_zero_queue(unsigned long long* queue, hipStream_t stream)
 hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream_t stream, bool adjoint)
 {
     if (adjoint)
-        hipLaunchKernelGGL(walk_f64_kernel<true>, dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+        hipLaunchKernelGGL((walk_kernel<true, false, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
     else
-        hipLaunchKernelGGL(walk_f64_kernel<false>, dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+        hipLaunchKernelGGL((walk_kernel<true, false, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -415,23 +555,42 @@ hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cf
 {
     if (adjoint) {
         if (kahan)
-            hipLaunchKernelGGL((walk_f32_kernel<true, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+            hipLaunchKernelGGL((walk_kernel<false, true, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
         else
-            hipLaunchKernelGGL((walk_f32_kernel<false, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+            hipLaunchKernelGGL((walk_kernel<false, false, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
     } else {
         if (kahan)
-            hipLaunchKernelGGL((walk_f32_kernel<true, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+            hipLaunchKernelGGL((walk_kernel<false, true, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
         else
-            hipLaunchKernelGGL((walk_f32_kernel<false, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+            hipLaunchKernelGGL((walk_kernel<false, false, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
     }
     return hipGetLastError();
 }
 
 hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu)
 {
-    const void* fn = precision == FK_F64 ? (const void*)walk_f64_kernel<false>
-                   : precision == FK_MIXED_KAHAN ? (const void*)walk_f32_kernel<true, false>
-                                                 : (const void*)walk_f32_kernel<false, false>;
+    const void* fn = precision == FK_F64 ? (const void*)walk_kernel<true, false, false>
+                   : precision == FK_MIXED_KAHAN ? (const void*)walk_kernel<false, true, false>
+                                                 : (const void*)walk_kernel<false, false, false>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
+}
+
+hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream)
+{
+    if (a.precision == FK_F64)
+        hipLaunchKernelGGL((batch_walk_kernel<true, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+    else if (a.precision == FK_MIXED_KAHAN)
+        hipLaunchKernelGGL((batch_walk_kernel<false, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+    else
+        hipLaunchKernelGGL((batch_walk_kernel<false, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu)
+{
+    const void* fn = precision == FK_F64 ? (const void*)batch_walk_kernel<true, false>
+                   : precision == FK_MIXED_KAHAN ? (const void*)batch_walk_kernel<false, true>
+                                                 : (const void*)batch_walk_kernel<false, false>;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 

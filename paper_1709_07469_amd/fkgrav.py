@@ -20,7 +20,8 @@ import threading
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libfkgrav.so")
+# FKGRAV_LIB names another build of the library (e.g. for A/B timing)
+LIB_PATH = os.environ.get("FKGRAV_LIB") or os.path.join(_PKG, "libfkgrav.so")
 
 FK_OK, FK_EINVAL, FK_EDOMAIN, FK_EWORKSPACE, FK_EDEVICE, FK_ETRUNC, FK_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FK_F64, FK_MIXED_F64ACC, FK_MIXED_KAHAN = 0, 1, 2
