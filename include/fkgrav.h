@@ -263,6 +263,15 @@ fk_status fk_gz_adjoint(const double *stations, int64_t n_stations, const fk_box
                         const void *forward_workspace, size_t forward_workspace_bytes, const double *grad_out,
                         double *grad_rho, void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* Diagnostic: the random stream exactly as the walk kernels compute it.  For
+ * n_items Philox counters (DEVICE, 4 uint32 words each: block k, path p,
+ * station s, problem m) and the key taken from seed, writes (each output
+ * DEVICE and nullable) the Philox4x32-10 words (4 per item), the two normals
+ * of the FP64 stream and the four normals of the mixed-precision stream that
+ * the block yields. */
+fk_status fk_stream_blocks(const uint32_t *counters, int64_t n_items, uint64_t seed, uint32_t *words,
+                           double *normals_f64, float *normals_f32, void *hip_stream);
+
 /* Launch settings of the walk kernels (the autotuner's knobs).  block: threads
  * per block (64..256, multiple of 64); blocks_per_cu: resident blocks per
  * compute unit (0 = as many as fit); grab: largest number of walks a

@@ -742,6 +742,19 @@ fk_status fk_solve_gz(const double* stations, int64_t n_stations, const fk_box* 
     return solve(1, stations, n_stations, box, source, bc, params, out, workspace, workspace_bytes, hip_stream);
 }
 
+fk_status fk_stream_blocks(const uint32_t* counters, int64_t n_items, uint64_t seed, uint32_t* words,
+                           double* normals_f64, float* normals_f32, void* hip_stream)
+{
+    if (n_items < 0) return fail(FK_EINVAL, "n_items < 0");
+    if (n_items == 0) return FK_OK;
+    if (!counters) return fail(FK_EINVAL, "counters is NULL");
+    if (n_items > (1ll << 31)) return fail(FK_EUNSUPPORTED, "at most 2^31 items");
+    hipError_t e = fk::launch_stream_blocks(counters, n_items, (uint32_t)(seed & 0xffffffffull),
+                                            (uint32_t)(seed >> 32), words, normals_f64, normals_f32,
+                                            reinterpret_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? FK_OK : fail(FK_EDEVICE, "stream launch failed: %s", hipGetErrorString(e));
+}
+
 fk_status fk_set_launch(int32_t precision, const fk_launch* launch)
 {
     if (precision < 0 || precision > 2) return fail(FK_EINVAL, "unknown precision %d", precision);

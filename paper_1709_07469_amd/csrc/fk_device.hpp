@@ -41,18 +41,117 @@ __device__ __forceinline__ Block philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     return Block{c0, c1, c2, c3};
 }
 
+// ---------------------------------------------------------------------------
+// FP64 elementary functions for the Box-Muller transform, written for the
+// argument ranges it needs (gfx950 has no FP64 transcendental unit, and the
+// general library routines handle ranges and cases that never occur here).
+// ---------------------------------------------------------------------------
+
+// -2 ln u for u in (0, 1].  u = m 2^e with m in [sqrt(1/2), sqrt(2)), and
+// ln m = 2 atanh(s) with s = (m - 1)/(m + 1), |s| <= 0.1716, summed as
+// s * sum_k s^(2k) / (2k + 1) for k = 0..10 (truncation below 1e-18
+// relative); ln 2 in a high part with trailing zeros (so e * ln2_hi is exact)
+// and a low part.  Error about 1 ulp.
+__device__ __forceinline__ double neg2_log(double u)
+{
+    double m = __builtin_amdgcn_frexp_mant(u);   // [0.5, 1)
+    int e = __builtin_amdgcn_frexp_exp(u);
+    if (m < 0x1.6a09e667f3bcdp-1) {             // sqrt(1/2)
+        m = 2.0 * m;
+        e -= 1;
+    }
+    const double d = m + 1.0;
+    double r = __builtin_amdgcn_rcp(d);          // estimate of 1/d, refined twice
+    double t = fma(-d, r, 1.0);
+    r = fma(r, t, r);
+    t = fma(-d, r, 1.0);
+    r = fma(r, t, r);
+    const double n = m - 1.0;                    // exact
+    double q = n * r;
+    q = fma(fma(-d, q, n), r, q);                // s = (m - 1)/(m + 1)
+    const double z = q * q;
+    double p = 0x1.8618618618618p-5;             // 1/21
+    p = fma(p, z, 0x1.af286bca1af28p-5);         // 1/19
+    p = fma(p, z, 0x1.e1e1e1e1e1e1ep-5);         // 1/17
+    p = fma(p, z, 0x1.1111111111111p-4);         // 1/15
+    p = fma(p, z, 0x1.3b13b13b13b14p-4);         // 1/13
+    p = fma(p, z, 0x1.745d1745d1746p-4);         // 1/11
+    p = fma(p, z, 0x1.c71c71c71c71cp-4);         // 1/9
+    p = fma(p, z, 0x1.2492492492492p-3);         // 1/7
+    p = fma(p, z, 0x1.999999999999ap-3);         // 1/5
+    p = fma(p, z, 0x1.5555555555555p-2);         // 1/3
+    p = fma(p, z, 1.0);
+    const double ts = (4.0 * q) * p;             // -2 ln m = -4 atanh(s)
+    const double fe = -2.0 * (double)e;
+    return fma(fe, 0x1.62e42fee00000p-1, fma(fe, 0x1.a39ef35793c76p-33, -ts));
+}
+
+// sqrt(x) for x >= 0: hardware reciprocal square-root estimate, two
+// Goldschmidt iterations on (g = x y, h = y/2), and a final residual
+// correction.
+__device__ __forceinline__ double sqrt_nonneg(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    g = fma(fma(-g, g, x), h, g);
+    return x > 0.0 ? g : 0.0;
+}
+
+// sin and cos of 2 pi u for u in (0, 1].  x = 2u is reduced exactly to
+// r = x - q/2 in [-1/4, 1/4] (q = nearest integer to 2x); sin(pi r) and
+// cos(pi r) are their Taylor series to r^17 and r^18 (truncation below
+// 1e-17); the quadrant q mod 4 swaps and negates them.
+__device__ __forceinline__ void sincos_2pi(double u, double& s, double& c)
+{
+    const double x = 2.0 * u;
+    const double q = __builtin_rint(2.0 * x);
+    const double r = fma(-0.5, q, x);
+    const double z = r * r;
+    double ps = 0x1.aaec32af93359p-21;
+    ps = fma(ps, z, -0x1.6fadb9f155744p-16);
+    ps = fma(ps, z, 0x1.e8f434d018d63p-12);
+    ps = fma(ps, z, -0x1.e3074fde8871fp-8);
+    ps = fma(ps, z, 0x1.50783487ee782p-4);
+    ps = fma(ps, z, -0x1.32d2cce62bd86p-1);
+    ps = fma(ps, z, 0x1.466bc6775aae2p+1);
+    ps = fma(ps, z, -0x1.4abbce625be53p+2);
+    ps = fma(ps, z, 0x1.921fb54442d18p+1);      // pi
+    const double sv = r * ps;
+    double pc = -0x1.2a0c591af8314p-23;
+    pc = fma(pc, z, 0x1.20c62c2f2d7f5p-18);
+    pc = fma(pc, z, -0x1.b6e24f44b128fp-14);
+    pc = fma(pc, z, 0x1.f9d38a3763cc3p-10);
+    pc = fma(pc, z, -0x1.a6d1f2a204a8cp-6);
+    pc = fma(pc, z, 0x1.e1f506891babbp-3);
+    pc = fma(pc, z, -0x1.55d3c7e3cbffap+0);
+    pc = fma(pc, z, 0x1.03c1f081b5ac4p+2);
+    pc = fma(pc, z, -0x1.3bd3cc9be45dep+2);
+    const double cv = fma(pc, z, 1.0);
+    const int qi = (int)q & 3;
+    const double ss = (qi & 1) ? cv : sv;
+    const double cc = (qi & 1) ? sv : cv;
+    s = (qi & 2) ? -ss : ss;
+    c = ((qi + 1) & 2) ? -cc : cc;
+}
+
 // FP64 stream: one block -> two 53-bit uniforms in (0, 1] -> one Box-Muller
-// pair (cosine branch first).  The angle 2 pi U is evaluated as sincospi(2U),
-// which needs no reduction by pi.
+// pair (cosine branch first): z0 = R cos(2 pi U2), z1 = R sin(2 pi U2),
+// R = sqrt(-2 ln U1).
 __device__ __forceinline__ void normals_f64(const Block& b, double& z0, double& z1)
 {
     const uint64_t a = ((((uint64_t)b.w1) << 21) | (uint64_t)(b.w0 >> 11)) + 1ull;
     const uint64_t c = ((((uint64_t)b.w3) << 21) | (uint64_t)(b.w2 >> 11)) + 1ull;
     const double u1 = (double)a * 0x1p-53;
     const double u2 = (double)c * 0x1p-53;
-    const double r = sqrt(-2.0 * log(u1));
+    const double r = sqrt_nonneg(neg2_log(u1));
     double s, co;
-    sincospi(2.0 * u2, &s, &co);
+    sincos_2pi(u2, s, co);
     z0 = r * co;
     z1 = r * s;
 }

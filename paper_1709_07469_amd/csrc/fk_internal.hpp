@@ -180,6 +180,8 @@ hipError_t launch_adjoint_combine(const int64_t* counts, int64_t n_stations, int
                                   const fk_stat* fwd, double scale, double* grad_rho, hipStream_t stream);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream);
 hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu);
+hipError_t launch_stream_blocks(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
+                                double* z64, float* z32, hipStream_t stream);
 
 // Batched solve: descriptor upload (by value through kernel arguments, so a
 // captured graph replays it), the persistent walk kernel over all problems,

@@ -595,6 +595,41 @@ hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu)
 }
 
 // ---------------------------------------------------------------------------
+// Diagnostic: the random stream as the walk kernels compute it.
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void stream_blocks_kernel(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
+                                     double* z64, float* z32)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Block b = philox10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], key0, key1);
+    if (words) {
+        words[4 * i] = b.w0;
+        words[4 * i + 1] = b.w1;
+        words[4 * i + 2] = b.w2;
+        words[4 * i + 3] = b.w3;
+    }
+    if (z64) normals_f64(b, z64[2 * i], z64[2 * i + 1]);
+    if (z32) {
+        normals_f32(b.w0, b.w1, z32[4 * i], z32[4 * i + 1]);
+        normals_f32(b.w2, b.w3, z32[4 * i + 2], z32[4 * i + 3]);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_stream_blocks(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
+                                double* z64, float* z32, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stream_blocks_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, ctr, n, key0,
+                       key1, words, z64, z32);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint helpers.
 // ---------------------------------------------------------------------------
 namespace {

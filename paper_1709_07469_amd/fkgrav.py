@@ -113,6 +113,8 @@ def lib():
             for nm in ("fk_potential_adjoint", "fk_gz_adjoint"):
                 getattr(L, nm).argtypes = [p, i64, p, p, p, p, p, p, sz, p, p, p, sz, p]
                 getattr(L, nm).restype = i32
+            L.fk_stream_blocks.argtypes = [p, i64, C.c_uint64, p, p, p, p]
+            L.fk_stream_blocks.restype = i32
             L.fk_set_launch.argtypes = [i32, p]
             L.fk_set_launch.restype = i32
             L.fk_get_launch.argtypes = [i32, p]
@@ -228,6 +230,12 @@ def fk_gz_adjoint(stations, box, source, bc, params, fwd_out, fwd_workspace, gra
     """grad_rho (cuda float64, one per voxel) <- sum_s grad_out[s] d g_z,s / d rho."""
     _adjoint_call("fk_gz_adjoint", stations, box, source, bc, params, fwd_out, fwd_workspace, grad_out,
                   grad_rho, workspace, stream)
+
+
+def fk_stream_blocks(counters, seed: int, words=None, normals_f64=None, normals_f32=None, stream=None) -> None:
+    """counters: cuda int32/uint32 tensor (n, 4); outputs cuda tensors or None."""
+    _check(lib().fk_stream_blocks(_ptr(counters), int(counters.shape[0]), int(seed), _ptr(words), _ptr(normals_f64),
+                                  _ptr(normals_f32), _stream_handle(stream)))
 
 
 def fk_set_launch(precision: int, block: int, blocks_per_cu: int = 0, grab: int = 32) -> None:
