@@ -41,8 +41,7 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 def algorithmic_ops_per_step(precision: str) -> float:
     """Full-rate VALU lane-operation slots one Euler-Maruyama step of the
     benchmark problem needs (one analytic prism, overshoot exit), counted
-    from the method's arithmetic with gfx950 issue costs (derivation in
-    DESIGN.md, table "Algorithmic work per step").
+    from the method's arithmetic with gfx950 issue costs.
 
     Philox4x32-10 block: 10 rounds x (2 v_mad_u64_u32 at 4 slots + 2 v_xor3
     at 1 slot) = 100 slots.  FP64 stream: 1.5 blocks, 3 normals from 1.5
@@ -203,9 +202,8 @@ def main():
                     help="also run one device-to-device copy of this many bytes (calibrates HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 (the multi-GPU design -- path "
-              "ranges per GPU merged by an all-gather of per-station statistics -- is described in DESIGN.md "
-              "and not implemented)", file=sys.stderr, flush=True)
+        print("bench.py: runs on one GPU only; --gpus must be 1 (running on several GPUs -- path ranges "
+              "per GPU merged by an all-gather of per-station statistics -- is not implemented)", file=sys.stderr, flush=True)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

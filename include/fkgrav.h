@@ -15,7 +15,7 @@
  *   whose mean estimates the potential u(x0) solving Laplace(u) = 4 pi G rho,
  *   u = g on the boundary (u < 0 for positive mass; the paper's walk
  *   gamma = sqrt(2) W of eq. 2 is the same process run twice as fast, so its
- *   Delta t equals dt/2).  Station results are the sample mean (eq. 10), the
+ *   Delta t equals dt/2).  Station results are the sample mean (eq. 11), the
  *   unbiased sample variance and the standard error.
  *   fk_solve_gz estimates g_z = du/dz (eq. 6) by the central difference of
  *   section 4.2, (u(x0 + h e_z) - u(x0 - h e_z)) / (2h), with both walks of a
@@ -60,7 +60,7 @@ typedef enum {
     FK_EWORKSPACE = -3,    /* workspace smaller than fk_workspace_bytes() or misaligned */
     FK_EDEVICE = -4,       /* a HIP runtime call failed */
     FK_ETRUNC = -5,        /* reserved: strict mode reports truncated walks through fk_stat */
-    FK_EUNSUPPORTED = -6   /* a size limit of this build is exceeded (see FK_MAX_*) */
+    FK_EUNSUPPORTED = -6   /* a size limit of the library is exceeded (see FK_MAX_*) */
 } fk_status;
 
 typedef enum {
@@ -154,7 +154,7 @@ typedef struct {
 /* Per-station result.  For fk_solve_gz the samples are the pair differences
  * and the step counts are those of both walks of a pair. */
 typedef struct {
-    double mean;                 /* sample mean of the untruncated samples (eq. 10) */
+    double mean;                 /* sample mean of the untruncated samples (eq. 11) */
     double var;                  /* unbiased sample variance */
     double se;                   /* standard error sqrt(var / n) */
     int64_t n;                   /* untruncated samples */
@@ -272,6 +272,15 @@ fk_status fk_gz_adjoint(const double *stations, int64_t n_stations, const fk_box
 fk_status fk_stream_blocks(const uint32_t *counters, int64_t n_items, uint64_t seed, uint32_t *words,
                            double *normals_f64, float *normals_f32, void *hip_stream);
 
+/* Moving-average smoothing of a station profile (paper section 4.1): value k
+ * is replaced by the mean of the values in the widest window of at most
+ * `span` (odd) points centred on k that fits in the profile, so the window
+ * shrinks symmetrically near the ends.  With standard errors se (HOST,
+ * nullable) of independent stations, out_se[k] = sqrt(sum se_j^2) / w.  All
+ * arrays HOST, length n. */
+fk_status fk_moving_average(const double *values, const double *se, int64_t n, int32_t span, double *out_values,
+                            double *out_se);
+
 /* Launch settings of the walk kernels (the autotuner's knobs).  block: threads
  * per block (64..256, multiple of 64); blocks_per_cu: resident blocks per
  * compute unit (0 = as many as fit); grab: largest number of walks a
@@ -284,6 +293,19 @@ typedef struct {
 } fk_launch;
 
 fk_status fk_set_launch(int32_t precision, const fk_launch *launch);
+
+/* Autotuner: solves the given problem (kind 0 = potential, 1 = g_z; same
+ * arguments as fk_solve_potential) once untimed and once timed with HIP
+ * events for every candidate launch setting -- block 64/128/256 threads,
+ * resident blocks per CU at the occupancy limit or half of it, queue runs of
+ * 16/32/64 walks -- installs the fastest for params->precision (as
+ * fk_set_launch) and returns it in *best (and its time in *best_ms,
+ * nullable).  Every setting gives the same results bit for bit; only the
+ * time differs.  Waits for the stream.  Tune on a reduced walk count of the
+ * target workload: a call runs 36 solves. */
+fk_status fk_autotune(int32_t kind, const double *stations, int64_t n_stations, const fk_box *box,
+                      const fk_source *source, const fk_boundary *bc, const fk_params *params, fk_stat *out,
+                      void *workspace, size_t workspace_bytes, void *hip_stream, fk_launch *best, double *best_ms);
 fk_status fk_get_launch(int32_t precision, fk_launch *launch);
 
 /* Kernel timing (tracing aid).  fk_timing_enable(1) makes every later solve

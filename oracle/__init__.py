@@ -95,6 +95,8 @@ def lib():
             L.fko_occupation.argtypes = [i32, p, i64, p, p, p, p, i64, i64, p, p, i32]
             L.fko_occupation.restype = i32
             L.fko_max_threads.restype = i32
+            L.fko_moving_average.argtypes = [p, p, i64, i32, p, p]
+            L.fko_moving_average.restype = i32
             _lib = L
     return _lib
 
@@ -295,6 +297,16 @@ def occupation(prob, kind, i_begin, i_end, stream=None, threads=0, **overrides):
     if rc != 0:
         raise ValueError("oracle: occupation needs a voxel grid")
     return cp, cm
+
+
+def moving_average(values, se=None, span=5):
+    v = _f64(values).ravel()
+    e = None if se is None else _f64(se).ravel()
+    out = np.empty_like(v)
+    oe = None if e is None else np.empty_like(e)
+    if lib().fko_moving_average(_ptr(v), _ptr(e), len(v), int(span), _ptr(out), _ptr(oe)) != 0:
+        raise ValueError("span must be a positive odd number")
+    return out, oe
 
 
 def max_threads():

@@ -10,7 +10,7 @@
  * independently and meet only through the seeded inputs the tests build.
  *
  * What it computes (paper section 2, eqs. 1-6 and the per-walk algorithm of
- * section 2.3), in the sign and time convention of the build:
+ * section 2.3), in the sign and time convention used throughout:
  *   - X is standard 3-D Brownian motion started at a station x0 and stepped by
  *     Euler-Maruyama, x_{n+1} = x_n + sqrt(dt) * Z_n, Z_n ~ N(0, I_3).  The
  *     paper's walk gamma = sqrt(2) W (eq. 2) is the same process at twice the
@@ -24,7 +24,7 @@
  *     u(x0) = E[g(X_tau)] - (1/2) E[int_0^tau 4 pi G rho(X_s) ds]
  *     which solves Laplace(u) = 4 pi G rho with u = g on the boundary
  *     (eqs. 3-5 with the physical sign of the potential).
- *   - The station estimate is the sample mean of eq. 10, with the unbiased
+ *   - The station estimate is the sample mean of eq. 11, with the unbiased
  *     sample variance and standard error.
  *   - g_z = du/dz by the central difference of eq. 6 / section 4.2, using
  *     the same random stream at x0 + h e_z and x0 - h e_z.
@@ -590,7 +590,7 @@ int fko_run_paths(int32_t kind, const double *stations, int64_t n_stations,
     return 0;
 }
 
-/* Station statistics of eq. 10 from per-path samples, in path order:
+/* Station statistics of eq. 11 from per-path samples, in path order:
  * n = untruncated samples, mean = sum/n, var = sum (u - mean)^2 / (n - 1),
  * se = sqrt(var / n); mean_steps and max_steps over all paths. */
 void fko_station_stats(const double *u, const uint32_t *steps, int64_t n_paths, fko_stat *out)
@@ -665,6 +665,30 @@ int fko_occupation(int32_t kind, const double *stations, int64_t n_stations,
                 walk(&P, xm, sm, p, &S, xe, &n, cm);
             }
         }
+    }
+    return 0;
+}
+
+/* Moving averages of a station profile (paper section 4.1): the mean over
+ * the largest centred window of at most `span` points that fits; standard
+ * errors of independent values combine as sqrt(sum se^2) / width. */
+int fko_moving_average(const double *v, const double *se, int64_t n, int span, double *out, double *out_se)
+{
+    if (span < 1 || span % 2 == 0) return -1;
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t half = span / 2;
+        int64_t left = k, right = n - 1 - k;
+        int64_t r = half < left ? half : left;
+        r = r < right ? r : right;
+        double acc = 0.0, acc2 = 0.0;
+        int64_t cnt = 0;
+        for (int64_t j = k - r; j <= k + r; ++j) {
+            acc += v[j];
+            if (se) acc2 += se[j] * se[j];
+            cnt++;
+        }
+        out[k] = acc / (double)cnt;
+        if (se) out_se[k] = sqrt(acc2) / (double)cnt;
     }
     return 0;
 }

@@ -1,6 +1,5 @@
 """Builds libfkgrav.so, the gfx950 HIP library behind include/fkgrav.h, in
-place with hipcc.  Every call recompiles (the build check compiles from
-source each time)."""
+place with hipcc.  Every call recompiles from source."""
 from __future__ import annotations
 
 import os

@@ -755,6 +755,95 @@ fk_status fk_stream_blocks(const uint32_t* counters, int64_t n_items, uint64_t s
     return e == hipSuccess ? FK_OK : fail(FK_EDEVICE, "stream launch failed: %s", hipGetErrorString(e));
 }
 
+fk_status fk_autotune(int32_t kind, const double* stations, int64_t n_stations, const fk_box* box,
+                      const fk_source* source, const fk_boundary* bc, const fk_params* params, fk_stat* out,
+                      void* workspace, size_t workspace_bytes, void* hip_stream, fk_launch* best, double* best_ms)
+{
+    fk_status st = check_params(kind, n_stations, params);
+    if (st != FK_OK) return st;
+    if (!best) return fail(FK_EINVAL, "best is NULL");
+    const int precision = params->precision;
+    fk_launch keep;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        keep = g_launch[precision];
+    }
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(FK_EDEVICE, "hipEventCreate failed");
+    const int blocks[3] = {64, 128, 256};
+    const int grabs[3] = {16, 32, 64};
+    double best_t = 1e300;
+    fk_launch best_l = keep;
+    st = FK_OK;
+    for (int bi = 0; bi < 3 && st == FK_OK; ++bi) {
+        int occ = 0;
+        if (fk::walk_occupancy(precision, blocks[bi], &occ) != hipSuccess || occ <= 0) continue;
+        const int bpcs[2] = {0, occ > 1 ? occ / 2 : 1};
+        for (int pi = 0; pi < 2 && st == FK_OK; ++pi) {
+            for (int gi = 0; gi < 3 && st == FK_OK; ++gi) {
+                {
+                    std::lock_guard<std::mutex> lk(g_mu);
+                    g_launch[precision] = fk_launch{blocks[bi], bpcs[pi], grabs[gi], 0};
+                }
+                float ms = 0.0f;
+                // one untimed run, then one timed run
+                for (int rep = 0; rep < 2 && st == FK_OK; ++rep) {
+                    if (rep == 1) (void)hipEventRecord(e0, stream);
+                    st = solve(kind, stations, n_stations, box, source, bc, params, out, workspace, workspace_bytes,
+                               hip_stream);
+                    if (rep == 1) (void)hipEventRecord(e1, stream);
+                }
+                if (st != FK_OK) break;
+                if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    st = fail(FK_EDEVICE, "timing failed");
+                    break;
+                }
+                if (ms < best_t) {
+                    best_t = ms;
+                    best_l = fk_launch{blocks[bi], bpcs[pi], grabs[gi], 0};
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_launch[precision] = st == FK_OK ? best_l : keep;
+    }
+    if (st != FK_OK) return st;
+    *best = best_l;
+    if (best_ms) *best_ms = best_t;
+    return FK_OK;
+}
+
+fk_status fk_moving_average(const double* values, const double* se, int64_t n, int32_t span, double* out_values,
+                            double* out_se)
+{
+    if (n < 0) return fail(FK_EINVAL, "n < 0");
+    if (span < 1 || span % 2 == 0) return fail(FK_EINVAL, "span must be a positive odd number, got %d", span);
+    if (n > 0 && (!values || !out_values)) return fail(FK_EINVAL, "NULL values");
+    if (se && !out_se) return fail(FK_EINVAL, "se given without out_se");
+    const int64_t half = span / 2;
+    for (int64_t k = 0; k < n; ++k) {
+        // the widest window centred on k that fits: k - r .. k + r
+        int64_t r = half;
+        if (k < r) r = k;
+        if (n - 1 - k < r) r = n - 1 - k;
+        double sum = 0.0, var = 0.0;
+        for (int64_t j = k - r; j <= k + r; ++j) {
+            sum += values[j];
+            if (se) var += se[j] * se[j];
+        }
+        const double w = (double)(2 * r + 1);
+        out_values[k] = sum / w;
+        if (se) out_se[k] = std::sqrt(var) / w;
+    }
+    return FK_OK;
+}
+
 fk_status fk_set_launch(int32_t precision, const fk_launch* launch)
 {
     if (precision < 0 || precision > 2) return fail(FK_EINVAL, "unknown precision %d", precision);

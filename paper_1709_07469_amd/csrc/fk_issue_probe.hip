@@ -1,7 +1,9 @@
 // fk_issue_probe.hip -- measures, on the GPU it runs on, the VALU issue cost
 // of the operations one Euler-Maruyama step of the walk kernels is made of:
 // a Philox4x32-10 block, an FP64 and an FP32 Box-Muller pair (uniform bits to
-// two normals), and FP64 / FP32 fused multiply-adds.  Each lane runs 8
+// two normals), the rest of a step (position update, density of one analytic
+// prism, trapezoid sum, exit test) in FP64 and in FP32 with an FP64 sum, and
+// FP64 / FP32 fused multiply-adds.  Each lane runs 8
 // independent dependency chains whose every result feeds the next input, so
 // nothing folds; the cost is reported in full-rate lane-slots (one slot = one
 // lane-operation at the chip's peak VALU issue rate, CUs x 64 x clock).
@@ -13,6 +15,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <type_traits>
 
 #include "fk_device.hpp"
 
@@ -131,6 +134,49 @@ __global__ void __launch_bounds__(256) fma32_probe(uint32_t* out, uint32_t seed)
     out[blockIdx.x * blockDim.x + threadIdx.x] = (uint32_t)s;
 }
 
+// The step body of the walk kernels for one analytic prism, normals read
+// from LDS (not VALU work); a walk that leaves the box restarts at its start.
+template <bool F64>
+__global__ void __launch_bounds__(256) step_probe(uint32_t* out, uint32_t seed)
+{
+    using T = typename std::conditional<F64, double, float>::type;
+    __shared__ T zs[192];
+    for (int i = threadIdx.x; i < 192; i += blockDim.x) zs[i] = (T)((int)((i * 37 + seed) % 97) - 48) * (T)0.04;
+    __syncthreads();
+    const T lo[3] = {T(0), T(0), T(-500)}, hi[3] = {T(1000), T(1000), T(100)};
+    const T q[6] = {T(400), T(450), T(-300), T(600), T(550), T(-150)};
+    const T sdt = T(2), rho0 = T(300);
+    T x[kChains][3], rp[kChains];
+    double S[kChains];
+    for (int j = 0; j < kChains; ++j) {
+        x[j][0] = T(62.5) + T(125) * (T)((threadIdx.x + j) & 7);
+        x[j][1] = T(62.5) + T(125) * (T)(blockIdx.x & 7);
+        x[j][2] = T(0);
+        rp[j] = T(0);
+        S[j] = 0.0;
+    }
+    for (int i = 0; i < kIter * 4; ++i) {
+        const int b = (i * 3) % 189;
+#pragma unroll
+        for (int j = 0; j < kChains; ++j) {
+            const T y0 = fma(sdt, zs[b + (j & 3)], x[j][0]);
+            const T y1 = fma(sdt, zs[b + 1], x[j][1]);
+            const T y2 = fma(sdt, zs[b + 2], x[j][2]);
+            const bool in = y0 >= q[0] && y0 < q[3] && y1 >= q[1] && y1 < q[4] && y2 >= q[2] && y2 < q[5];
+            const T rn = in ? rho0 : T(0);
+            S[j] = S[j] + (F64 ? (double)(rp[j] + rn) : ((double)rp[j] + (double)rn));
+            const bool o = y0 <= lo[0] || y0 >= hi[0] || y1 <= lo[1] || y1 >= hi[1] || y2 <= lo[2] || y2 >= hi[2];
+            x[j][0] = o ? T(500) : y0;
+            x[j][1] = o ? T(500) : y1;
+            x[j][2] = o ? T(0) : y2;
+            rp[j] = o ? T(0) : rn;
+        }
+    }
+    double s = 0.0;
+    for (int j = 0; j < kChains; ++j) s += S[j] + (double)x[j][0] + (double)x[j][2];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = (uint32_t)(int64_t)s;
+}
+
 typedef void (*Probe)(uint32_t*, uint32_t);
 
 }  // namespace
@@ -151,6 +197,8 @@ int main()
     } items[] = {{"philox_block", philox_probe, (double)kIter},
                  {"box_muller_pair_f64", bm64_probe, (double)(kIter / 8)},
                  {"box_muller_pair_f32", bm32_probe, (double)kIter},
+                 {"step_f64", step_probe<true>, (double)(kIter * 4)},
+                 {"step_f32_f64sum", step_probe<false>, (double)(kIter * 4)},
                  {"fma_f64", fma64_probe, (double)(kIter * 8)},
                  {"fma_f32", fma32_probe, (double)(kIter * 8)}};
     hipEvent_t e0, e1;

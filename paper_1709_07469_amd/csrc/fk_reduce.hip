@@ -1,7 +1,7 @@
 // fk_reduce.hip -- the per-walk samples u_p = g(x_e) - 2 pi G (dt/2) S from the
 // walks' exit records (Dirichlet data read at the exit point, FP64), and the
 // per-station statistics of the samples (the sample mean of arXiv:1709.07469
-// eq. 10, with the unbiased variance and standard error), with the paired
+// eq. 11, with the unbiased variance and standard error), with the paired
 // central difference of eq. 6 for g_z.
 //
 // Deterministic two-level reduction: the N samples of a station are cut into

@@ -115,6 +115,10 @@ def lib():
                 getattr(L, nm).restype = i32
             L.fk_stream_blocks.argtypes = [p, i64, C.c_uint64, p, p, p, p]
             L.fk_stream_blocks.restype = i32
+            L.fk_autotune.argtypes = [i32, p, i64, p, p, p, p, p, p, sz, p, p, p]
+            L.fk_autotune.restype = i32
+            L.fk_moving_average.argtypes = [p, p, i64, i32, p, p]
+            L.fk_moving_average.restype = i32
             L.fk_set_launch.argtypes = [i32, p]
             L.fk_set_launch.restype = i32
             L.fk_get_launch.argtypes = [i32, p]
@@ -236,6 +240,28 @@ def fk_stream_blocks(counters, seed: int, words=None, normals_f64=None, normals_
     """counters: cuda int32/uint32 tensor (n, 4); outputs cuda tensors or None."""
     _check(lib().fk_stream_blocks(_ptr(counters), int(counters.shape[0]), int(seed), _ptr(words), _ptr(normals_f64),
                                   _ptr(normals_f32), _stream_handle(stream)))
+
+
+def fk_autotune(kind, stations, box, source, bc, params, out, workspace, stream=None):
+    """Runs the library's launch-setting sweep; returns ({block,
+    blocks_per_cu, grab}, milliseconds)."""
+    best = fk_launch()
+    ms = C.c_double()
+    _check(lib().fk_autotune(int(kind), _ptr(stations), int(stations.shape[0]), C.byref(box), C.byref(source),
+                             C.byref(bc), C.byref(params), _ptr(out), _ptr(workspace), int(workspace.numel()),
+                             _stream_handle(stream), C.byref(best), C.byref(ms)))
+    return {"block": best.block, "blocks_per_cu": best.blocks_per_cu, "grab": best.grab}, ms.value
+
+
+def fk_moving_average(values, se=None, span: int = 5):
+    """Centred moving average of a station profile (host); returns
+    (smoothed values, their standard errors or None)."""
+    v = np.ascontiguousarray(values, dtype=np.float64).ravel()
+    e = None if se is None else np.ascontiguousarray(se, dtype=np.float64).ravel()
+    ov = np.empty_like(v)
+    oe = None if e is None else np.empty_like(e)
+    _check(lib().fk_moving_average(_ptr(v), _ptr(e), len(v), int(span), _ptr(ov), _ptr(oe)))
+    return ov, oe
 
 
 def fk_set_launch(precision: int, block: int, blocks_per_cu: int = 0, grab: int = 32) -> None:

@@ -3,7 +3,7 @@
 This module only builds inputs: boxes, station sets, density models (analytic
 prisms and spheres, voxel grids filled from voxel-aligned prisms) and the
 parameters of a run.  It holds none of the estimator's arithmetic, so both the
-HIP library's binding and the independent CPU checker can consume the same
+HIP library's binding and the independent CPU oracle can consume the same
 ``Problem`` objects.
 
 Workloads follow the paper's set-up (section 3: a homogeneous 100 m cube of

@@ -1,7 +1,7 @@
 // Prints Philox4x32-10 blocks computed by rocRAND's header-only engine on the
 // host, for (counter, key) rows read from stdin as six hex words
 // c0 c1 c2 c3 k0 k1.  An independent implementation of the generator
-// (Salmon et al., SC'11) used to pin the CPU checker's own Philox.
+// (Salmon et al., SC'11) used to pin the oracle's own Philox.
 #include <rocrand/rocrand_philox4x32_10.h>
 #include <cstdio>
 

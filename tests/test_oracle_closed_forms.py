@@ -1,4 +1,4 @@
-"""Pins for the closed forms the checker uses as boundary data and as exact
+"""Pins for the closed forms the oracle uses as boundary data and as exact
 targets: the homogeneous prism's Newtonian integral (the paper compares with
 the cube's analytic potential, section 1 and section 3) and its vertical
 derivative (the analytic g_z of section 4.2), and the uniform ball.

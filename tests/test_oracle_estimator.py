@@ -1,4 +1,4 @@
-"""Pins for the CPU checker's estimator (paper section 2.3 and eq. 10) against
+"""Pins for the oracle's estimator (paper section 2.3 and eq. 11) against
 what the mathematics fixes, at any time step:
 
 * harmonic data and no source: E[u_p] = h(x0) exactly under the overshoot
@@ -104,6 +104,9 @@ def test_uniform_ball_gz_crn_against_closed_form_difference():
     # the common-random-number pair is far less noisy than independent walks
     stats_ind, _, _ = oracle.solve(pr.replace(pairing=W.PAIR_INDEPENDENT, paths_per_station=2000), 1)
     assert np.all(np.array([s["se"] for s in stats_ind]) > 2.0 * np.array([s["se"] for s in stats]))
+    # independent pairs (the paper's practice) estimate the same difference
+    zi = _zscores(stats_ind, fd_exact)
+    assert np.all(np.abs(zi) < 4.0), zi
 
 
 def test_si_prism_cfg2_subset_against_closed_form():

@@ -1,5 +1,5 @@
-"""Pins for the CPU checker's random streams (Philox4x32-10 and the
-Box-Muller maps), independent of the checker's own code:
+"""Pins for the oracle's random streams (Philox4x32-10 and the
+Box-Muller maps), independent of the oracle's own code:
 
 * Philox words against rocRAND's header-only host engine, an independent
   implementation of the same published generator (Salmon et al., SC'11),
