@@ -56,7 +56,7 @@ class BC(C.Structure):
 class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("seed", C.c_uint64), ("G", C.c_double), ("h", C.c_double),
                 ("stream", C.c_int32), ("exit_rule", C.c_int32), ("pairing", C.c_int32),
-                ("pad_", C.c_int32), ("max_steps", C.c_int64), ("problem_id", C.c_uint32),
+                ("domain", C.c_int32), ("max_steps", C.c_int64), ("problem_id", C.c_uint32),
                 ("pad2_", C.c_uint32), ("path_offset", C.c_int64)]
 
 
@@ -158,6 +158,7 @@ class _Marshalled:
         prm.stream = int(stream)
         prm.exit_rule = int(g("exit_rule", 0))
         prm.pairing = int(g("pairing", 0))
+        prm.domain = int(g("domain", 0))
         prm.max_steps = int(g("max_steps", 1 << 30))
         prm.problem_id = int(g("problem_id", 0))
         prm.path_offset = int(g("path_offset", 0))

@@ -18,8 +18,10 @@
  *   - The source integral is the trapezoid rule of section 2.3:
  *     I = (dt/2) * sum_n (rho(x_n) + rho(x_{n+1})), the exiting step included
  *     (the paper accumulates before it tests for the exit).
- *   - The walk stops at the first n with x_{n+1} on or outside the box
+ *   - The walk stops at the first n with x_{n+1} on or outside the domain
  *     (exit time of eq. 3).  Dirichlet data g is read at the exit point.
+ *     The domain is a box, or the ball inscribed in a cubic box (the
+ *     paper's experiments use a ball of radius 10 km, section 3).
  *   - Per path u_p = g(x_e) - 2*pi*G*I, the sample of
  *     u(x0) = E[g(X_tau)] - (1/2) E[int_0^tau 4 pi G rho(X_s) ds]
  *     which solves Laplace(u) = 4 pi G rho with u = g on the boundary
@@ -74,6 +76,7 @@ enum { FKO_BC_ZERO = 0, FKO_BC_QUADRATIC = 1, FKO_BC_POINT_MASSES = 2,
 enum { FKO_EXIT_OVERSHOOT = 0, FKO_EXIT_INTERSECT = 1 };
 enum { FKO_STREAM_F64 = 0, FKO_STREAM_F32 = 1 };
 enum { FKO_PAIR_CRN = 0, FKO_PAIR_INDEPENDENT = 1 };
+enum { FKO_DOMAIN_BOX = 0, FKO_DOMAIN_BALL = 1 };
 
 typedef struct {
     int32_t kind;
@@ -90,7 +93,7 @@ typedef struct {
     int32_t stream;         /* FKO_STREAM_F64 or FKO_STREAM_F32 */
     int32_t exit_rule;
     int32_t pairing;
-    int32_t pad_;
+    int32_t domain;         /* FKO_DOMAIN_BOX, or FKO_DOMAIN_BALL: the ball inscribed in the (cubic) box */
     int64_t max_steps;
     uint32_t problem_id;
     uint32_t pad2_;
@@ -444,11 +447,51 @@ typedef struct {
     const fko_params *prm;
 } fko_problem;
 
-static int outside(const fko_box *box, const double x[3])
+/* The ball domain: centre (lo + hi) / 2 and radius (hi_x - lo_x) / 2 of its
+ * box. */
+static void ball_of(const fko_box *box, double c[3], double *r2)
 {
-    for (int c = 0; c < 3; ++c)
-        if (x[c] <= box->lo[c] || x[c] >= box->hi[c]) return 1;
+    for (int k = 0; k < 3; ++k) c[k] = 0.5 * (box->lo[k] + box->hi[k]);
+    double r = 0.5 * (box->hi[0] - box->lo[0]);
+    *r2 = r * r;
+}
+
+/* |x - c|^2 with the products of y and x fused into the running sum. */
+static double dist2(const double x[3], const double c[3])
+{
+    double d0 = x[0] - c[0], d1 = x[1] - c[1], d2 = x[2] - c[2];
+    return fma(d0, d0, fma(d1, d1, d2 * d2));
+}
+
+/* On or beyond the boundary (a point on the boundary has left, eq. 3). */
+static int outside(const fko_box *box, int domain, const double x[3])
+{
+    if (domain == FKO_DOMAIN_BALL) {
+        double c[3], r2;
+        ball_of(box, c, &r2);
+        return dist2(x, c) >= r2;
+    }
+    for (int k = 0; k < 3; ++k)
+        if (x[k] <= box->lo[k] || x[k] >= box->hi[k]) return 1;
     return 0;
+}
+
+/* INTERSECT on the ball: the point of the segment x -> xn on the sphere,
+ * x + t (xn - x) with t the root in (0, 1] of |x + t v - c|^2 = R^2, written
+ * t = -C / (B + sqrt(B^2 - A C)) (A = |v|^2, B = (x - c).v, C = |x - c|^2 -
+ * R^2 < 0), which has no cancellation. */
+static void intersect_ball(const fko_box *box, const double x[3], const double xn[3], double xe[3])
+{
+    double c[3], r2;
+    ball_of(box, c, &r2);
+    double v[3], a[3];
+    for (int k = 0; k < 3; ++k) { v[k] = xn[k] - x[k]; a[k] = x[k] - c[k]; }
+    double A = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double B = a[0] * v[0] + a[1] * v[1] + a[2] * v[2];
+    double C = (a[0] * a[0] + a[1] * a[1] + a[2] * a[2]) - r2;
+    double t = -C / (B + sqrt(B * B - A * C));
+    if (t > 1.0) t = 1.0;
+    for (int k = 0; k < 3; ++k) xe[k] = fma(t, v[k], x[k]);
 }
 
 /* Exit point on the segment x -> xn under the INTERSECT rule: the first face
@@ -499,9 +542,12 @@ static int walk(const fko_problem *P, const double x0[3], uint32_t sctr, uint32_
         double rn = fko_rho(P->src, xn);
         S = S + (rp + rn);
         if (counts) { add_count(P->src, counts, x); add_count(P->src, counts, xn); }
-        if (outside(P->box, xn)) {
+        if (outside(P->box, prm->domain, xn)) {
             n = n + 1;
-            if (prm->exit_rule == FKO_EXIT_INTERSECT) intersect_point(P->box, x, xn, xe);
+            if (prm->exit_rule == FKO_EXIT_INTERSECT && prm->domain == FKO_DOMAIN_BALL)
+                intersect_ball(P->box, x, xn, xe);
+            else if (prm->exit_rule == FKO_EXIT_INTERSECT)
+                intersect_point(P->box, x, xn, xe);
             else { xe[0] = xn[0]; xe[1] = xn[1]; xe[2] = xn[2]; }
             *S_out = S;
             *steps = n;

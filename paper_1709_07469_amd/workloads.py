@@ -15,6 +15,10 @@ five concrete configurations used for testing and measurement:
   cfg3  128^3 voxel grid of 5 random prisms, 16x16 stations, mixed precision
   cfg4  32 random voxel models of uneven size in one batched launch
   cfg5  32^3 voxel grid, 32 stations, adjoint d g_z / d rho
+
+and the paper's own model (section 3): the ball of radius 10 km with zero
+Dirichlet data around the 100 m cube, observed on the lines and the grid of
+its experiments 1-3 (lengths in km).
 """
 from __future__ import annotations
 
@@ -29,14 +33,19 @@ BC_ZERO, BC_QUADRATIC, BC_POINT_MASSES, BC_PRISMS, BC_FACE_GRID = 0, 1, 2, 3, 4
 EXIT_OVERSHOOT, EXIT_INTERSECT = 0, 1
 PREC_F64, PREC_MIXED_F64ACC, PREC_MIXED_KAHAN = 0, 1, 2
 PAIR_CRN, PAIR_INDEPENDENT = 0, 1
+DOMAIN_BOX, DOMAIN_BALL = 0, 1
 
 G_SI = 6.674e-11
+G_KM = 6.674e-20          # km^3 kg^-1 s^-2
 
 
 @dataclass
 class Problem:
-    """One forward problem: box domain, stations, density, boundary data and
+    """One forward problem: domain, stations, density, boundary data and
     run parameters.  Arrays are host numpy arrays.
+
+    The domain is the box [box_lo, box_hi], or with domain = DOMAIN_BALL the
+    ball inscribed in it (the box must then be a cube).
 
     rho is indexed [k, j, i] (x fastest) over voxels whose (0,0,0) corner is
     grid_origin with edge lengths grid_spacing.  prisms rows are
@@ -65,6 +74,7 @@ class Problem:
     precision: int = PREC_F64
     exit_rule: int = EXIT_OVERSHOOT
     pairing: int = PAIR_CRN
+    domain: int = DOMAIN_BOX
     max_steps: int = 1 << 30
     problem_id: int = 0
     path_offset: int = 0
@@ -246,3 +256,49 @@ def cfg5_fd_voxels(n_vox=32 ** 3, count=64, seed=55):
     """The 64 voxel indices probed by the finite-difference check of cfg5."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.sort(rng.choice(n_vox, size=count, replace=False))
+
+
+# --------------------------------------------------------------------------
+# The paper's model (section 3), in km: lengths in km make the reported run
+# times consistent with the expected exit time of a 10 km ball.
+# --------------------------------------------------------------------------
+
+PAPER_R_KM = 10.0
+PAPER_CUBE_KM = np.array([0.0, 0.0, 0.0, 0.1, 0.1, 0.1])
+PAPER_RHO = 2.0e12        # 2000 kg/m^3 in kg/km^3
+
+
+def paper_exp1_stations() -> np.ndarray:
+    """Experiment 1: the line y = 50 m, z = 200 m, x = -100 m .. 200 m every 10 m."""
+    x = np.round(np.arange(-10, 21) * 0.01, 12)
+    return np.stack([x, np.full_like(x, 0.05), np.full_like(x, 0.2)], axis=1)
+
+
+def paper_exp2_stations() -> np.ndarray:
+    """Experiment 2: the vertical line x = y = 50 m, z = -100 m .. 200 m every 10 m."""
+    z = np.round(np.arange(-10, 21) * 0.01, 12)
+    return np.stack([np.full_like(z, 0.05), np.full_like(z, 0.05), z], axis=1)
+
+
+def paper_exp3_stations() -> np.ndarray:
+    """Experiment 3: a 21 x 11 grid in the plane y = 50 m, x spread evenly
+    over -100 m .. 200 m and z = 195 m .. 205 m every metre (z fastest)."""
+    x = np.linspace(-0.1, 0.2, 21)
+    z = np.round(0.2 + np.arange(-5, 6) * 0.001, 12)
+    X, Z = np.meshgrid(x, z, indexing="ij")
+    return np.stack([X.ravel(), np.full(X.size, 0.05), Z.ravel()], axis=1)
+
+
+def paper_ball(stations=None, dt_paper=0.01, paths_per_station=51200, precision=PREC_F64,
+               radius=PAPER_R_KM) -> Problem:
+    """The paper's model: ball of radius 10 km about the origin with zero
+    Dirichlet data, a homogeneous cube [0, 100 m]^3 of 2000 kg/m^3, G in km
+    units.  The paper's walk is sqrt(2) W with step sqrt(2 Delta t), the same
+    paths as standard Brownian motion with dt = 2 Delta t."""
+    st = paper_exp1_stations() if stations is None else np.asarray(stations, dtype=np.float64).reshape(-1, 3)
+    cube = np.concatenate([PAPER_CUBE_KM, [PAPER_RHO]])[None, :]
+    return Problem(
+        box_lo=np.full(3, -radius), box_hi=np.full(3, radius), stations=st,
+        dt=2.0 * dt_paper, paths_per_station=paths_per_station, seed=0, G=G_KM,
+        prisms=cube, bc_kind=BC_ZERO, precision=precision, domain=DOMAIN_BALL,
+        name="paper-ball-10km")
