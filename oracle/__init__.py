@@ -75,6 +75,8 @@ def lib():
             L.fko_philox4x32_10.argtypes = [p, p, p]
             L.fko_normal.argtypes = [i32, u64, u32, u32, u32, i64]
             L.fko_normal.restype = d
+            L.fko_bridge_uniform.argtypes = [i32, u64, u32, u32, u32, i64]
+            L.fko_bridge_uniform.restype = d
             L.fko_rho.argtypes = [p, p]
             L.fko_rho.restype = d
             L.fko_voxel_index.argtypes = [p, p]
@@ -178,6 +180,10 @@ def philox4x32_10(counter, key):
 
 def normal(stream, seed, m, s, p, j):
     return lib().fko_normal(int(stream), int(seed), int(m), int(s), int(p), int(j))
+
+
+def bridge_uniform(stream, seed, m, s, p, n):
+    return lib().fko_bridge_uniform(int(stream), int(seed), int(m), int(s), int(p), int(n))
 
 
 def rho_at(prob, x):

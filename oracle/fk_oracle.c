@@ -73,7 +73,7 @@ typedef struct {
 
 enum { FKO_BC_ZERO = 0, FKO_BC_QUADRATIC = 1, FKO_BC_POINT_MASSES = 2,
        FKO_BC_PRISMS = 3, FKO_BC_FACE_GRID = 4 };
-enum { FKO_EXIT_OVERSHOOT = 0, FKO_EXIT_INTERSECT = 1 };
+enum { FKO_EXIT_OVERSHOOT = 0, FKO_EXIT_INTERSECT = 1, FKO_EXIT_BRIDGE = 2 };
 enum { FKO_STREAM_F64 = 0, FKO_STREAM_F32 = 1 };
 enum { FKO_PAIR_CRN = 0, FKO_PAIR_INDEPENDENT = 1 };
 enum { FKO_DOMAIN_BOX = 0, FKO_DOMAIN_BALL = 1 };
@@ -204,6 +204,34 @@ static double stream_normal(fko_stream *st, int64_t j)
     int64_t k = j / per;
     if (k != st->cached_block) stream_block(st, k);
     return st->z[j % per];
+}
+
+/* Uniforms of the Brownian-bridge exit test: step n uses slot n mod q of
+ * block 2^31 + floor(n / q) of the walk's Philox stream, q = 2 for the FP64
+ * stream (53-bit uniforms from the word pairs (w1, w0) and (w3, w2), as U1
+ * and U2 above) and q = 4 for the FP32 stream (24-bit uniforms).  Block
+ * indices of the normals stay below 2^31 while walks are shorter than 2^30
+ * steps. */
+static double bridge_uniform(const fko_stream *st, int64_t n)
+{
+    int q = (st->stream == FKO_STREAM_F64) ? 2 : 4;
+    uint32_t ctr[4] = {0x80000000u + (uint32_t)(n / q), st->p, st->s, st->m};
+    uint32_t key[2] = {(uint32_t)st->seed, (uint32_t)(st->seed >> 32)};
+    uint32_t w[4];
+    fko_philox4x32_10(ctr, key, w);
+    int slot = (int)(n % q);
+    if (st->stream == FKO_STREAM_F64) {
+        uint32_t hi = w[2 * slot + 1], lo = w[2 * slot];
+        return (double)((((uint64_t)hi << 21) | (uint64_t)(lo >> 11)) + 1u) * 0x1p-53;
+    }
+    return (double)((w[slot] >> 8) + 1u) * 0x1p-24;
+}
+
+double fko_bridge_uniform(int32_t stream, uint64_t seed, uint32_t m, uint32_t s, uint32_t p, int64_t n)
+{
+    fko_stream st;
+    stream_init(&st, stream, seed, m, s, p);
+    return bridge_uniform(&st, n);
 }
 
 double fko_normal(int32_t stream, uint64_t seed, uint32_t m, uint32_t s, uint32_t p, int64_t j)
@@ -514,6 +542,45 @@ static void intersect_point(const fko_box *box, const double x[3], const double 
     xe[cbest] = face;
 }
 
+/* Brownian-bridge exit test (paper section 2.3, remark on the exit time;
+ * Gobet 2000): a standard Brownian motion that goes from distance a to
+ * distance b > 0 of a plane in time dt has touched the plane in between with
+ * probability exp(-2 a b / dt).  For a step x -> xn with both ends inside,
+ * every face of the box (or the tangent plane of the sphere) contributes
+ * such a probability p_f; the walk is stopped in this step when its uniform
+ * U satisfies U <= 1 - prod_f (1 - p_f).  The exit point is xn projected onto
+ * the face with the largest p_f (ties: -x, +x, -y, +y, -z, +z order), or
+ * radially onto the sphere.  Returns 1 and fills xe when the walk stops. */
+static int bridge_exit(const fko_box *box, int domain, double dt, double U, const double x[3],
+                       const double xn[3], double xe[3])
+{
+    if (domain == FKO_DOMAIN_BALL) {
+        double c[3], r2;
+        ball_of(box, c, &r2);
+        double R = sqrt(r2);
+        double a = R - sqrt(dist2(x, c)), b = R - sqrt(dist2(xn, c));
+        double p = exp(-2.0 * a * b / dt);
+        if (!(U <= p)) return 0;
+        double r = sqrt(dist2(xn, c));
+        for (int k = 0; k < 3; ++k) xe[k] = c[k] + R * ((xn[k] - c[k]) / r);
+        return 1;
+    }
+    double keep = 1.0, pbest = -1.0;
+    int fbest = 0;
+    for (int f = 0; f < 6; ++f) {
+        int k = f / 2;
+        double a = (f % 2) ? box->hi[k] - x[k] : x[k] - box->lo[k];
+        double b = (f % 2) ? box->hi[k] - xn[k] : xn[k] - box->lo[k];
+        double p = exp(-2.0 * a * b / dt);
+        keep *= 1.0 - p;
+        if (p > pbest) { pbest = p; fbest = f; }
+    }
+    if (!(U <= 1.0 - keep)) return 0;
+    for (int k = 0; k < 3; ++k) xe[k] = xn[k];
+    xe[fbest / 2] = (fbest % 2) ? box->hi[fbest / 2] : box->lo[fbest / 2];
+    return 1;
+}
+
 /* Adds the trapezoid weights of one walk to counts[voxel]: one per end of
  * every step whose end lies in the grid. */
 static void add_count(const fko_source *src, uint64_t *counts, const double x[3])
@@ -544,13 +611,19 @@ static int walk(const fko_problem *P, const double x0[3], uint32_t sctr, uint32_
         if (counts) { add_count(P->src, counts, x); add_count(P->src, counts, xn); }
         if (outside(P->box, prm->domain, xn)) {
             n = n + 1;
-            if (prm->exit_rule == FKO_EXIT_INTERSECT && prm->domain == FKO_DOMAIN_BALL)
+            if (prm->exit_rule != FKO_EXIT_OVERSHOOT && prm->domain == FKO_DOMAIN_BALL)
                 intersect_ball(P->box, x, xn, xe);
-            else if (prm->exit_rule == FKO_EXIT_INTERSECT)
+            else if (prm->exit_rule != FKO_EXIT_OVERSHOOT)
                 intersect_point(P->box, x, xn, xe);
             else { xe[0] = xn[0]; xe[1] = xn[1]; xe[2] = xn[2]; }
             *S_out = S;
             *steps = n;
+            return 0;
+        }
+        if (prm->exit_rule == FKO_EXIT_BRIDGE &&
+            bridge_exit(P->box, prm->domain, prm->dt, bridge_uniform(&st, n), x, xn, xe)) {
+            *S_out = S;
+            *steps = n + 1;
             return 0;
         }
         x[0] = xn[0]; x[1] = xn[1]; x[2] = xn[2];

@@ -30,7 +30,7 @@ import numpy as np
 # Boundary-data kinds, exit rules, precisions and g_z pairings (the values of
 # the C interface's enumerations).
 BC_ZERO, BC_QUADRATIC, BC_POINT_MASSES, BC_PRISMS, BC_FACE_GRID = 0, 1, 2, 3, 4
-EXIT_OVERSHOOT, EXIT_INTERSECT = 0, 1
+EXIT_OVERSHOOT, EXIT_INTERSECT, EXIT_BRIDGE = 0, 1, 2
 PREC_F64, PREC_MIXED_F64ACC, PREC_MIXED_KAHAN = 0, 1, 2
 PAIR_CRN, PAIR_INDEPENDENT = 0, 1
 DOMAIN_BOX, DOMAIN_BALL = 0, 1
