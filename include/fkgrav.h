@@ -71,7 +71,17 @@ typedef enum {
 
 typedef enum {
     FK_EXIT_OVERSHOOT = 0, /* data read at the first point on/outside the box (unbiased for harmonic data) */
-    FK_EXIT_INTERSECT = 1  /* data read where the last step's segment first meets the boundary */
+    FK_EXIT_INTERSECT = 1, /* data read where the last step's segment first meets the boundary */
+    FK_EXIT_BRIDGE = 2     /* INTERSECT plus the Brownian-bridge test of the paper's remark on the exit
+                            * time (section 2.3; Gobet 2000): a step whose two ends lie inside is a stop
+                            * with probability 1 - prod_f (1 - exp(-2 a_f b_f / dt)), a_f and b_f the
+                            * distances of its ends to face f (ball: to the sphere, one term).  The
+                            * walk's uniform for step n is slot n mod q of Philox block 2^31 + n / q of
+                            * its stream (q = 2 FP64: 53-bit uniforms from word pairs (w1,w0), (w3,w2);
+                            * q = 4 FP32: 24-bit uniforms (w >> 8) + 1) * 2^-24); it stops when
+                            * U <= that probability, and the data is read at the step's end projected
+                            * onto the face with the largest probability (ties: -x, +x, -y, +y, -z, +z)
+                            * or radially onto the sphere.  Needs max_steps <= 2^30. */
 } fk_exit_rule;
 
 typedef enum {
@@ -134,6 +144,14 @@ typedef struct {
     int32_t face_n[6][2];
 } fk_boundary;
 
+/* The domain Omega of eq. 1.  FK_DOMAIN_BOX: the box itself.  FK_DOMAIN_BALL:
+ * the ball inscribed in the box, centre (lo + hi) / 2 and radius
+ * (hi[0] - lo[0]) / 2 -- the box must be a cube (edges equal to 1e-12
+ * relative) -- as in the experiments of section 3 (a ball of radius 10 km).
+ * A point x has left the ball when |x - c|^2 >= R^2, with |x - c|^2 =
+ * fma(d0, d0, fma(d1, d1, d2 * d2)).  FK_BC_FACE_GRID needs a box domain. */
+typedef enum { FK_DOMAIN_BOX = 0, FK_DOMAIN_BALL = 1 } fk_domain;
+
 /* Run parameters (paper section 3: N walks per station and time step Delta t). */
 typedef struct {
     int64_t paths_per_station;   /* N >= 2, path_offset + N <= 2^32 */
@@ -147,7 +165,7 @@ typedef struct {
     int32_t strict;              /* nonzero: FK_ETRUNC-style reporting via fk_stat.n_trunc only (reserved) */
     int64_t max_steps;           /* cap per walk, 1 .. 2^31-1; capped walks are excluded and counted */
     uint32_t problem_id;         /* counter word m */
-    uint32_t pad0;
+    int32_t domain;              /* fk_domain */
     int64_t path_offset;         /* first path index p */
 } fk_params;
 

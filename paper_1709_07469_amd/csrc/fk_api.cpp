@@ -120,8 +120,11 @@ fk_status check_params(int32_t kind, int64_t n_stations, const fk_params* p)
     if (!is_finite(p->G)) return fail(FK_EINVAL, "G must be finite");
     if (!(is_finite(p->h) && p->h >= 0.0)) return fail(FK_EINVAL, "h must be finite and >= 0");
     if (p->precision < 0 || p->precision > 2) return fail(FK_EINVAL, "unknown precision %d", p->precision);
-    if (p->exit_rule < 0 || p->exit_rule > 1) return fail(FK_EINVAL, "unknown exit_rule %d", p->exit_rule);
+    if (p->exit_rule < 0 || p->exit_rule > 2) return fail(FK_EINVAL, "unknown exit_rule %d", p->exit_rule);
+    if (p->exit_rule == FK_EXIT_BRIDGE && p->max_steps > (1ll << 30))
+        return fail(FK_EUNSUPPORTED, "the bridge exit test needs max_steps <= 2^30");
     if (p->pairing < 0 || p->pairing > 1) return fail(FK_EINVAL, "unknown pairing %d", p->pairing);
+    if (p->domain != FK_DOMAIN_BOX && p->domain != FK_DOMAIN_BALL) return fail(FK_EINVAL, "unknown domain %d", p->domain);
     if (p->max_steps < 1 || p->max_steps > 0x7fffffffll) return fail(FK_EINVAL, "max_steps must lie in [1, 2^31-1]");
     const int64_t npair = kind == 1 ? 2 : 1;
     if (n_stations > 0 && p->paths_per_station > (INT64_MAX / 16) / (npair * n_stations))
@@ -154,6 +157,33 @@ fk_status check_box(const fk_box* b)
         if (!(b->lo[c] < b->hi[c])) return fail(FK_EINVAL, "box lo[%d] must be < hi[%d]", c, c);
     }
     return FK_OK;
+}
+
+// The ball domain is the ball inscribed in a cubic box; face-grid data is
+// defined on box faces only.
+fk_status check_domain(const fk_box* b, const fk_params* p, const fk_boundary* bc)
+{
+    if (p->domain != FK_DOMAIN_BALL) return FK_OK;
+    const double w = b->hi[0] - b->lo[0];
+    for (int c = 1; c < 3; ++c)
+        if (std::fabs((b->hi[c] - b->lo[c]) - w) > 1e-12 * w)
+            return fail(FK_EINVAL, "a ball domain needs a cubic box (edge %d differs)", c);
+    if (bc && bc->kind == FK_BC_FACE_GRID) return fail(FK_EUNSUPPORTED, "face-grid data needs a box domain");
+    return FK_OK;
+}
+
+// Ball centre and squared radius, computed as the oracle defines them.
+void ball_of(const fk_box* b, double c[3], double* r2)
+{
+    for (int k = 0; k < 3; ++k) c[k] = 0.5 * (b->lo[k] + b->hi[k]);
+    const double r = 0.5 * (b->hi[0] - b->lo[0]);
+    *r2 = r * r;
+}
+
+double dist2(const double x[3], const double c[3])
+{
+    const double d0 = x[0] - c[0], d1 = x[1] - c[1], d2 = x[2] - c[2];
+    return std::fma(d0, d0, std::fma(d1, d1, d2 * d2));
 }
 
 fk_status check_source(const fk_source* s)
@@ -253,6 +283,24 @@ void fill_common(fk::WalkCommon& C, int32_t kind, const double* stations, int64_
     C.npair = kind == 1 ? 2 : 1;
     C.pairing = p->pairing;
     C.exit_rule = p->exit_rule;
+    C.domain = p->domain;
+    C.dt = p->dt;
+    C.dt_f = (float)p->dt;
+    // Bridge stops are skipped when both step ends lie delta = sqrt(K dt)
+    // inside every face: then each crossing probability is below exp(-2K)
+    // and their sum below the smallest uniform (2^-53 with K = 20 for the
+    // FP64 stream, 2^-24 with K = 10 for the FP32 one), so no stop is lost.
+    C.delta = std::sqrt((p->precision == FK_F64 ? 20.0 : 10.0) * p->dt);
+    C.delta_f = (float)C.delta;
+    if (p->domain == FK_DOMAIN_BALL) {
+        ball_of(box, C.ctr, &C.r2);
+        C.R = std::sqrt(C.r2);
+        C.deep2 = C.delta < C.R ? (C.R - C.delta) * (C.R - C.delta) : -1.0;
+        for (int c = 0; c < 3; ++c) C.ctr_f[c] = (float)C.ctr[c];
+        C.r2_f = (float)C.r2;
+        C.R_f = (float)C.R;
+        C.deep2_f = C.delta_f < C.R_f ? (C.R_f - C.delta_f) * (C.R_f - C.delta_f) : -1.0f;
+    }
 }
 
 void fill_bc(fk::BoundaryArgs& B, const fk_boundary* bc)
@@ -317,7 +365,10 @@ void fill_source_f32(fk::SourceF32& S, const fk_source* s)
         for (int c = 0; c < 5; ++c) S.spheres[j][c] = (float)s->spheres[5 * j + c];
 }
 
-fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false)
+// The general stepping loop (ball domain, bridge test) or the box loop.
+bool general_loop(const fk_params* p) { return p->domain == FK_DOMAIN_BALL || p->exit_rule == FK_EXIT_BRIDGE; }
+
+fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false, bool gen = false)
 {
     fk_launch l;
     {
@@ -330,8 +381,8 @@ fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool b
     if (cus <= 0) return fail(FK_EDEVICE, "could not query the compute-unit count");
     int bpc = l.blocks_per_cu;
     if (bpc <= 0) {
-        const hipError_t oe = batch ? fk::batch_occupancy(precision, l.block, &bpc)
-                                    : fk::walk_occupancy(precision, l.block, &bpc);
+        const hipError_t oe = batch ? fk::batch_occupancy(precision, l.block, &bpc, gen)
+                                    : fk::walk_occupancy(precision, l.block, &bpc, gen);
         if (oe != hipSuccess || bpc <= 0)
             return fail(FK_EDEVICE, "occupancy query failed for block %d", l.block);
     }
@@ -354,6 +405,7 @@ fk_status solve(int32_t kind, const double* stations, int64_t n_stations, const 
     if ((st = check_box(box)) != FK_OK) return st;
     if ((st = check_source(src)) != FK_OK) return st;
     if ((st = check_bc(bc)) != FK_OK) return st;
+    if ((st = check_domain(box, p, bc)) != FK_OK) return st;
     if (n_stations == 0) return FK_OK;
     if (!stations) return fail(FK_EINVAL, "stations is NULL");
     if (!out) return fail(FK_EINVAL, "out is NULL");
@@ -370,7 +422,7 @@ fk_status solve(int32_t kind, const double* stations, int64_t n_stations, const 
     char* ws = static_cast<char*>(workspace);
 
     fk::LaunchCfg cfg;
-    if ((st = plan_launch(p->precision, L.n_tasks, &cfg)) != FK_OK) return st;
+    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, general_loop(p))) != FK_OK) return st;
 
     fk::WalkCommon C;
     fill_common(C, kind, stations, n_stations, box, p, L, ws);
@@ -443,6 +495,7 @@ fk_status check_batch(const fk_problem* probs, int32_t n)
         if ((st = check_box(&P.box)) != FK_OK) return st;
         if ((st = check_source(&P.source)) != FK_OK) return st;
         if ((st = check_bc(&P.bc)) != FK_OK) return st;
+        if ((st = check_domain(&P.box, &P.params, &P.bc)) != FK_OK) return st;
         if (P.n_stations > 0 && !P.stations) return fail(FK_EINVAL, "problem %d: stations is NULL", m);
         if (P.out_offset < 0) return fail(FK_EINVAL, "problem %d: out_offset < 0", m);
         if (P.params.precision != probs[0].params.precision)
@@ -489,7 +542,9 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
     const int precision = probs[0].params.precision;
 
     fk::LaunchCfg cfg;
-    if ((st = plan_launch(precision, BL.n_tasks, &cfg, true)) != FK_OK) return st;
+    bool gen = false;
+    for (int32_t m = 0; m < n; ++m) gen = gen || general_loop(&probs[m].params);
+    if ((st = plan_launch(precision, BL.n_tasks, &cfg, true, gen)) != FK_OK) return st;
 
     std::vector<int64_t> task_off(n + 1, 0), block_off(n + 1, 0);
     int64_t station_base = 0;
@@ -543,7 +598,7 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
 
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     const bool timed = timing_begin(&ev, stream);
-    e = fk::launch_batch_walk(A, cfg, stream);
+    e = fk::launch_batch_walk(A, cfg, stream, gen);
     if (timed) timing_end(ev, stream);
     if (e != hipSuccess) return fail(FK_EDEVICE, "batch walk launch failed: %s", hipGetErrorString(e));
     e = fk::launch_batch_reduce(A, BL.n_blocks, BL.n_stations, stream);
@@ -579,6 +634,7 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
     if ((st = check_box(box)) != FK_OK) return st;
     if ((st = check_source(src)) != FK_OK) return st;
     if ((st = check_bc(bc)) != FK_OK) return st;
+    if ((st = check_domain(box, p, bc)) != FK_OK) return st;
     if (!src->rho) return fail(FK_EINVAL, "the adjoint needs a voxel grid (source.rho is NULL)");
     if (!grad_rho) return fail(FK_EINVAL, "grad_rho is NULL");
     const AdjLayout AL = make_adj_layout(n_stations, src);
@@ -599,7 +655,7 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
     int64_t* counts = reinterpret_cast<int64_t*>(ws + AL.counts);
 
     fk::LaunchCfg cfg;
-    if ((st = plan_launch(p->precision, L.n_tasks, &cfg)) != FK_OK) return st;
+    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, general_loop(p))) != FK_OK) return st;
     fk::WalkCommon C;
     fill_common(C, kind, stations, n_stations, box, p, L, nullptr);
     C.exits = nullptr;
@@ -714,10 +770,22 @@ fk_status fk_check_stations(const double* stations_host, int64_t n_stations, con
     fk_status st;
     if ((st = check_params(kind, n_stations, params)) != FK_OK) return st;
     if ((st = check_box(box)) != FK_OK) return st;
+    if ((st = check_domain(box, params, nullptr)) != FK_OK) return st;
     if (n_stations > 0 && !stations_host) return fail(FK_EINVAL, "stations is NULL");
     const double h = kind == 1 ? (params->h > 0.0 ? params->h : std::sqrt(params->dt)) : 0.0;
+    double ctr[3], r2 = 0.0;
+    if (params->domain == FK_DOMAIN_BALL) ball_of(box, ctr, &r2);
     for (int64_t s = 0; s < n_stations; ++s) {
         const double* x = stations_host + 3 * s;
+        if (params->domain == FK_DOMAIN_BALL) {
+            for (int w = 0; w < (kind == 1 ? 2 : 1); ++w) {
+                const double y[3] = {x[0], x[1], kind == 1 ? (w == 0 ? x[2] + h : x[2] - h) : x[2]};
+                if (!is_finite(x[0]) || !is_finite(x[1]) || !is_finite(x[2]) || !(dist2(y, ctr) < r2))
+                    return fail(FK_EDOMAIN, "station %lld is not strictly inside the ball%s", (long long)s,
+                                kind == 1 ? " (with +-h along z)" : "");
+            }
+            continue;
+        }
         for (int c = 0; c < 3; ++c) {
             const double d = c == 2 ? h : 0.0;
             if (!is_finite(x[c]) || !(x[c] - d > box->lo[c] && x[c] + d < box->hi[c]))
@@ -779,7 +847,8 @@ fk_status fk_autotune(int32_t kind, const double* stations, int64_t n_stations, 
     st = FK_OK;
     for (int bi = 0; bi < 3 && st == FK_OK; ++bi) {
         int occ = 0;
-        if (fk::walk_occupancy(precision, blocks[bi], &occ) != hipSuccess || occ <= 0) continue;
+        if (fk::walk_occupancy(precision, blocks[bi], &occ, general_loop(params)) != hipSuccess || occ <= 0)
+            continue;
         const int bpcs[2] = {0, occ > 1 ? occ / 2 : 1};
         for (int pi = 0; pi < 2 && st == FK_OK; ++pi) {
             for (int gi = 0; gi < 3 && st == FK_OK; ++gi) {

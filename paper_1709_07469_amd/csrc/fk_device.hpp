@@ -282,6 +282,36 @@ __device__ __forceinline__ void intersect_exit(const double* lo, const double* h
     e[cmin] = fmin;
 }
 
+// Squared distance |x - c|^2, the products of the first two axes fused into
+// the running sum (the ball domain's exit test).
+template <typename T>
+__device__ __forceinline__ T dist2(T x0, T x1, T x2, T c0, T c1, T c2)
+{
+    const T d0 = x0 - c0, d1 = x1 - c1, d2 = x2 - c2;
+    return fma(d0, d0, fma(d1, d1, d2 * d2));
+}
+
+// INTERSECT on the ball |x - c| = R: a + t (b - a) with t the root in (0, 1]
+// of |a + t v - c|^2 = R^2, written t = -C / (B + sqrt(B^2 - A C)) with
+// A = |v|^2, B = (a - c).v and C = |a - c|^2 - R^2 < 0 (no cancellation).
+__device__ __forceinline__ void intersect_ball(const double* c, double r2, const double a[3], const double b[3],
+                                               double e[3])
+{
+    double v[3], q[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[k] = b[k] - a[k];
+        q[k] = a[k] - c[k];
+    }
+    const double A = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double B = q[0] * v[0] + q[1] * v[1] + q[2] * v[2];
+    const double C = (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) - r2;
+    double t = -C / (B + sqrt(B * B - A * C));
+    if (t > 1.0) t = 1.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = fma(t, v[k], a[k]);
+}
+
 // ---------------------------------------------------------------------------
 // Dirichlet data.
 // ---------------------------------------------------------------------------

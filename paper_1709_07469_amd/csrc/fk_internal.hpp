@@ -83,7 +83,15 @@ struct WalkCommon {
     int32_t exit_rule;
     int32_t grab;              // largest queue claim per wavefront
     uint32_t total_waves;      // resident wavefronts of the launch
-    int32_t pad0;
+    int32_t domain;            // FK_DOMAIN_BOX / FK_DOMAIN_BALL
+    double ctr[3];             // ball domain: centre, squared radius, radius
+    double r2;
+    double R;
+    double dt;
+    double delta;              // Brownian bridge: a step whose ends both lie at least delta
+    double deep2;              // inside every face cannot be stopped; ball: (R - delta)^2 or -1
+    float ctr_f[3];
+    float r2_f, R_f, dt_f, delta_f, deep2_f;
     // adjoint replay only: signed trapezoid weights per (station, voxel), and
     // the forward solve's step counts (walks capped there are skipped)
     int64_t* counts;
@@ -179,7 +187,8 @@ hipError_t launch_fill_zero(int64_t* p, int64_t n, hipStream_t stream);
 hipError_t launch_adjoint_combine(const int64_t* counts, int64_t n_stations, int64_t nvox, const double* grad_out,
                                   const fk_stat* fwd, double scale, double* grad_rho, hipStream_t stream);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream);
-hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu);
+// gen: the general stepping loop (ball domain or Brownian-bridge test)
+hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, bool gen = false);
 hipError_t launch_stream_blocks(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
                                 double* z64, float* z32, hipStream_t stream);
 
@@ -187,8 +196,8 @@ hipError_t launch_stream_blocks(const uint32_t* ctr, int64_t n, uint32_t key0, u
 // captured graph replays it), the persistent walk kernel over all problems,
 // and the batched reduction.
 hipError_t launch_write_words(uint64_t* dst, const uint64_t* host_words, int64_t n_words, hipStream_t stream);
-hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream);
+hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, bool gen);
 hipError_t launch_batch_reduce(const BatchArgs& a, int64_t n_blocks, int64_t n_station_threads, hipStream_t stream);
-hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu);
+hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, bool gen = false);
 
 }  // namespace fk

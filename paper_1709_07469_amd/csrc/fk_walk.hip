@@ -147,6 +147,7 @@ __device__ __forceinline__ TaskInfo decode(const WalkCommon& C, uint64_t t)
 
 __device__ __forceinline__ bool strictly_inside(const WalkCommon& C, const double x[3])
 {
+    if (C.domain == FK_DOMAIN_BALL) return dist2(x[0], x[1], x[2], C.ctr[0], C.ctr[1], C.ctr[2]) < C.r2;
     return x[0] > C.lo[0] && x[0] < C.hi[0] && x[1] > C.lo[1] && x[1] < C.hi[1] && x[2] > C.lo[2] &&
            x[2] < C.hi[2];
 }
@@ -201,6 +202,17 @@ struct Prec<true> {
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f64(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo[c]; }
     __device__ static T hi(const WalkCommon& C, int c) { return C.hi[c]; }
+    __device__ static T ctr(const WalkCommon& C, int c) { return C.ctr[c]; }
+    __device__ static T r2(const WalkCommon& C) { return C.r2; }
+    __device__ static T radius(const WalkCommon& C) { return C.R; }
+    __device__ static T dt(const WalkCommon& C) { return C.dt; }
+    __device__ static T delta(const WalkCommon& C) { return C.delta; }
+    __device__ static T deep2(const WalkCommon& C) { return C.deep2; }
+    __device__ static T uniform(const Block& b, int j)
+    {
+        const uint32_t hi = j ? b.w3 : b.w1, lo = j ? b.w2 : b.w0;
+        return (double)((((uint64_t)hi << 21) | (uint64_t)(lo >> 11)) + 1u) * 0x1p-53;
+    }
     __device__ static T sdt(const WalkCommon& C) { return C.sdt; }
 };
 
@@ -220,6 +232,17 @@ struct Prec<false> {
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f32(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo_f[c]; }
     __device__ static T hi(const WalkCommon& C, int c) { return C.hi_f[c]; }
+    __device__ static T ctr(const WalkCommon& C, int c) { return C.ctr_f[c]; }
+    __device__ static T r2(const WalkCommon& C) { return C.r2_f; }
+    __device__ static T radius(const WalkCommon& C) { return C.R_f; }
+    __device__ static T dt(const WalkCommon& C) { return C.dt_f; }
+    __device__ static T delta(const WalkCommon& C) { return C.delta_f; }
+    __device__ static T deep2(const WalkCommon& C) { return C.deep2_f; }
+    __device__ static T uniform(const Block& b, int j)
+    {
+        const uint32_t w = j == 0 ? b.w0 : j == 1 ? b.w1 : j == 2 ? b.w2 : b.w3;
+        return (float)((w >> 8) + 1u) * 0x1p-24f;
+    }
     __device__ static T sdt(const WalkCommon& C) { return C.sdt_f; }
 };
 
@@ -243,7 +266,12 @@ struct LaneProblem {
     const WalkCommon* C;
     const typename Prec<F64>::Src* src;
     T sdt;
+    // box domain: the bounds; ball domain: (lo0, lo1, lo2) = centre,
+    // hi0 = squared radius, hi1 = radius, hi2 = (R - delta)^2 (the two never
+    // coexist, so they share registers)
     T lo0, lo1, lo2, hi0, hi1, hi2;
+    T dt, delta;               // Brownian-bridge test
+    bool ball, bridge;
     uint32_t key0, key1, pid;
     int64_t max_steps;
 
@@ -258,6 +286,18 @@ struct LaneProblem {
         hi0 = Prec<F64>::hi(c, 0);
         hi1 = Prec<F64>::hi(c, 1);
         hi2 = Prec<F64>::hi(c, 2);
+        ball = c.domain == FK_DOMAIN_BALL;
+        bridge = c.exit_rule == FK_EXIT_BRIDGE;
+        dt = Prec<F64>::dt(c);
+        delta = Prec<F64>::delta(c);
+        if (ball) {
+            lo0 = Prec<F64>::ctr(c, 0);
+            lo1 = Prec<F64>::ctr(c, 1);
+            lo2 = Prec<F64>::ctr(c, 2);
+            hi0 = Prec<F64>::r2(c);
+            hi1 = Prec<F64>::radius(c);
+            hi2 = Prec<F64>::deep2(c);
+        }
         key0 = c.key0;
         key1 = c.key1;
         pid = c.problem_id;
@@ -266,7 +306,9 @@ struct LaneProblem {
 };
 
 // One lane's walk.
-template <bool F64, bool KAHAN, bool ADJ>
+// GEN: the general stepping loop (ball domain, Brownian-bridge test);
+// without it the loop is the box domain's with the step-end exit test only.
+template <bool F64, bool KAHAN, bool ADJ, bool GEN>
 struct Walker {
     using T = typename Prec<F64>::T;
     uint64_t task;
@@ -275,13 +317,55 @@ struct Walker {
     float Sf, Sc;    // Kahan sum and compensation
     uint32_t n, k, sctr, pctr;
     bool active;
+    bool deep;       // the current point lies delta inside every face (bridge test)
     Scatter sc;
 
+    // delta inside every face (ball: |x - c|^2 <= (R - delta)^2)
+    __device__ __forceinline__ static bool deep_inside(const LaneProblem<F64>& P, T y0, T y1, T y2, T d2)
+    {
+        if (P.ball) return d2 <= P.hi2;
+        return y0 - P.lo0 >= P.delta && P.hi0 - y0 >= P.delta && y1 - P.lo1 >= P.delta && P.hi1 - y1 >= P.delta &&
+               y2 - P.lo2 >= P.delta && P.hi2 - y2 >= P.delta;
+    }
+
+    // Brownian-bridge test of step m from (x0, x1, x2) to y (both inside):
+    // returns the face the walk stopped at (0..5; 6 = the sphere) or -1.
+    __device__ __forceinline__ int bridge_stop(const LaneProblem<F64>& P, uint32_t m, T y0, T y1, T y2) const
+    {
+        constexpr int q = Prec<F64>::kNormals;
+        const Block b = philox10(0x80000000u + m / q, pctr, sctr, P.pid, P.key0, P.key1);
+        const T U = Prec<F64>::uniform(b, (int)(m % q));
+        if (P.ball) {
+            const T a = P.hi1 - sqrt(dist2(x0, x1, x2, P.lo0, P.lo1, P.lo2));
+            const T c = P.hi1 - sqrt(dist2(y0, y1, y2, P.lo0, P.lo1, P.lo2));
+            const T p = exp(T(-2) * a * c / P.dt);
+            return U <= p ? 6 : -1;
+        }
+        const T lo[3] = {P.lo0, P.lo1, P.lo2}, hi[3] = {P.hi0, P.hi1, P.hi2};
+        const T x[3] = {x0, x1, x2}, y[3] = {y0, y1, y2};
+        T keep = T(1), pbest = T(-1);
+        int fbest = 0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int j = f >> 1;
+            const T a = (f & 1) ? hi[j] - x[j] : x[j] - lo[j];
+            const T c = (f & 1) ? hi[j] - y[j] : y[j] - lo[j];
+            const T p = exp(T(-2) * a * c / P.dt);
+            keep *= T(1) - p;
+            if (p > pbest) {
+                pbest = p;
+                fbest = f;
+            }
+        }
+        return U <= T(1) - keep ? fbest : -1;
+    }
+
     // One Euler-Maruyama step with normals (z0, z1, z2).  Returns true when
-    // the walk ends here: it left the box (a = last inside point, e = the
-    // first point outside) or it reached max_steps (capped).
+    // the walk ends here, with how = 0: it left the domain (a = last inside
+    // point, e = the first point outside); how = 1: it reached max_steps;
+    // how = 2 + f: the bridge test stopped it at face f (e = the step's end).
     __device__ __forceinline__ bool step(const LaneProblem<F64>& P, T z0, T z1, T z2, T& a0, T& a1, T& a2, T& e0,
-                                         T& e1, T& e2, bool& capped)
+                                         T& e1, T& e2, int& how)
     {
         const T y0 = Prec<F64>::fmat(P.sdt, z0, x0);
         const T y1 = Prec<F64>::fmat(P.sdt, z1, x1);
@@ -301,11 +385,25 @@ struct Walker {
             }
         }
         n += 1;
-        const bool out = y0 <= P.lo0 || y0 >= P.hi0 || y1 <= P.lo1 || y1 >= P.hi1 || y2 <= P.lo2 || y2 >= P.hi2;
-        if (ADJ) sc.add(Prec<F64>::voxel(*P.src, y0, y1, y2), out ? 1 : 2);
-        if (out) {
+        bool out;
+        T d2 = T(0);
+        if (GEN && P.ball) {
+            d2 = dist2(y0, y1, y2, P.lo0, P.lo1, P.lo2);
+            out = d2 >= P.hi0;
+        } else {
+            out = y0 <= P.lo0 || y0 >= P.hi0 || y1 <= P.lo1 || y1 >= P.hi1 || y2 <= P.lo2 || y2 >= P.hi2;
+        }
+        int stop = -1;
+        if (GEN && P.bridge && !out) {
+            const bool deep_y = deep_inside(P, y0, y1, y2, d2);
+            if (!(deep && deep_y)) stop = bridge_stop(P, n - 1, y0, y1, y2);
+            deep = deep_y;
+        }
+        if (ADJ) sc.add(Prec<F64>::voxel(*P.src, y0, y1, y2), (out || stop >= 0) ? 1 : 2);
+        if (out || stop >= 0) {
             a0 = x0; a1 = x1; a2 = x2;
             e0 = y0; e1 = y1; e2 = y2;
+            how = out ? 0 : 2 + stop;
             return true;
         }
         x0 = y0;
@@ -313,29 +411,45 @@ struct Walker {
         x2 = y2;
         rp = rn;
         if ((int64_t)n == P.max_steps) {
-            capped = true;
+            how = 1;
             return true;
         }
         return false;
     }
 
     // Stores the walk's exit record (or flushes its scatter) and frees the lane.
-    __device__ __forceinline__ void finish(const LaneProblem<F64>& P, T a0, T a1, T a2, T e0, T e1, T e2,
-                                           bool capped)
+    __device__ __forceinline__ void finish(const LaneProblem<F64>& P, T a0, T a1, T a2, T e0, T e1, T e2, int how)
     {
+        const bool capped = how == 1;
         if (ADJ) {
             sc.flush();
         } else {
             const WalkCommon& C = *P.C;
             double e[3] = {0.0, 0.0, 0.0};
-            if (!capped) {
+            if (GEN && how >= 2) {
+                // bridge stop: the step's end projected onto the face
                 e[0] = (double)e0;
                 e[1] = (double)e1;
                 e[2] = (double)e2;
-                if (C.exit_rule == FK_EXIT_INTERSECT) {
+                const int f = how - 2;
+                if (f == 6) {
+                    const double r = sqrt(dist2(e[0], e[1], e[2], C.ctr[0], C.ctr[1], C.ctr[2]));
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) e[j] = C.ctr[j] + C.R * ((e[j] - C.ctr[j]) / r);
+                } else {
+                    e[f >> 1] = (f & 1) ? C.hi[f >> 1] : C.lo[f >> 1];
+                }
+            } else if (!capped) {
+                e[0] = (double)e0;
+                e[1] = (double)e1;
+                e[2] = (double)e2;
+                if (C.exit_rule != FK_EXIT_OVERSHOOT) {
                     const double a[3] = {(double)a0, (double)a1, (double)a2};
                     const double b[3] = {(double)e0, (double)e1, (double)e2};
-                    intersect_exit(C.lo, C.hi, a, b, e);
+                    if (C.domain == FK_DOMAIN_BALL)
+                        intersect_ball(C.ctr, C.r2, a, b, e);
+                    else
+                        intersect_exit(C.lo, C.hi, a, b, e);
                 }
             }
             const double sum = (!F64 && KAHAN) ? ((double)Sf - (double)Sc) : S;
@@ -349,7 +463,7 @@ struct Walker {
 // ---------------------------------------------------------------------------
 // The kernel body.
 // ---------------------------------------------------------------------------
-template <bool F64, bool KAHAN, bool ADJ, bool BATCH, class Args>
+template <bool F64, bool KAHAN, bool ADJ, bool BATCH, bool GEN, class Args>
 __device__ __forceinline__ void walk_body(const Args& A)
 {
     using T = typename Prec<F64>::T;
@@ -367,6 +481,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
         P.src = nullptr;
         P.sdt = T(0);
         P.lo0 = P.lo1 = P.lo2 = P.hi0 = P.hi1 = P.hi2 = T(0);
+        P.ball = false;
         P.key0 = P.key1 = P.pid = 0;
         P.max_steps = 0;
     } else {
@@ -374,13 +489,14 @@ __device__ __forceinline__ void walk_body(const Args& A)
         P.load(A.c, A.src);
     }
     Pool pool{0ull, 0ull, Q.n_tasks, false};
-    Walker<F64, KAHAN, ADJ> W;
+    Walker<F64, KAHAN, ADJ, GEN> W;
     W.active = false;
     W.task = 0;
     W.x0 = W.x1 = W.x2 = W.rp = T(0);
     W.S = 0.0;
     W.Sf = W.Sc = 0.0f;
     W.n = W.k = W.sctr = W.pctr = 0;
+    W.deep = false;
     W.sc = Scatter{nullptr, -1, 0, 1};
     const int wave = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
@@ -428,6 +544,11 @@ __device__ __forceinline__ void walk_body(const Args& A)
                     W.sc.add(Prec<F64>::voxel(*P.src, W.x0, W.x1, W.x2), 1);
                 } else {
                     W.rp = Prec<F64>::rho(*P.src, W.x0, W.x1, W.x2);
+                }
+                W.deep = false;
+                if (GEN && P.bridge) {
+                    const T d2 = P.ball ? dist2(W.x0, W.x1, W.x2, P.lo0, P.lo1, P.lo2) : T(0);
+                    W.deep = W.deep_inside(P, W.x0, W.x1, W.x2, d2);
                 }
                 W.active = true;
             }
@@ -477,7 +598,8 @@ __device__ __forceinline__ void walk_body(const Args& A)
             wave_sync_lds();
             if (W.active) {
                 const int n_steps = B * NPB / 3;      // a multiple of MACRO
-                bool done = false, capped = false;
+                bool done = false;
+                int how = 0;
                 T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
                 for (int s0 = 0; s0 < n_steps && !done; s0 += MACRO) {
                     T zz[3 * MACRO];
@@ -489,11 +611,11 @@ __device__ __forceinline__ void walk_body(const Args& A)
 #pragma unroll
                     for (int s = 0; s < MACRO; ++s) {
                         if (!done)
-                            done = W.step(P, zz[3 * s], zz[3 * s + 1], zz[3 * s + 2], a0, a1, a2, e0, e1, e2, capped);
+                            done = W.step(P, zz[3 * s], zz[3 * s + 1], zz[3 * s + 2], a0, a1, a2, e0, e1, e2, how);
                     }
                 }
                 W.k += (uint32_t)B;
-                if (done) W.finish(P, a0, a1, a2, e0, e1, e2, capped);
+                if (done) W.finish(P, a0, a1, a2, e0, e1, e2, how);
             }
             wave_sync_lds();
             continue;
@@ -509,29 +631,46 @@ __device__ __forceinline__ void walk_body(const Args& A)
             Prec<F64>::normals(bl, z + NPB * b);
         }
         W.k += 3;
-        bool done = false, capped = false;
+        bool done = false;
+        int how = 0;
         T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
 #pragma unroll
         for (int s = 0; s < MACRO; ++s) {
-            if (!done) done = W.step(P, z[3 * s], z[3 * s + 1], z[3 * s + 2], a0, a1, a2, e0, e1, e2, capped);
+            if (!done) done = W.step(P, z[3 * s], z[3 * s + 1], z[3 * s + 2], a0, a1, a2, e0, e1, e2, how);
         }
-        if (done) W.finish(P, a0, a1, a2, e0, e1, e2, capped);
+        if (done) W.finish(P, a0, a1, a2, e0, e1, e2, how);
     }
 }
 
-// FP64 walks are held to 4 wavefronts per SIMD (128 VGPRs): measured a few
-// percent faster than 3 wavefronts without the limit, despite a small spill.
-template <bool F64, bool KAHAN, bool ADJ>
-__global__ void __launch_bounds__(256, F64 ? 4 : 1)
+// Minimum resident 256-thread blocks per CU the compiler must allow (this
+// bounds the VGPRs per lane: 4 blocks = 4 wavefronts per SIMD = 128 VGPRs).
+// FP64 walks are held to 4 wavefronts per SIMD: measured faster than 3
+// wavefronts without the limit, despite a small spill.
+#ifndef FK_F64_BLOCKS_PER_CU
+#define FK_F64_BLOCKS_PER_CU 4
+#endif
+#ifndef FK_F32_BLOCKS_PER_CU
+#define FK_F32_BLOCKS_PER_CU 1
+#endif
+#ifndef FK_BATCH_F64_BLOCKS_PER_CU
+#define FK_BATCH_F64_BLOCKS_PER_CU 1
+#endif
+#ifndef FK_BATCH_F32_BLOCKS_PER_CU
+#define FK_BATCH_F32_BLOCKS_PER_CU 1
+#endif
+
+template <bool F64, bool KAHAN, bool ADJ, bool GEN>
+__global__ void __launch_bounds__(256, F64 ? FK_F64_BLOCKS_PER_CU : FK_F32_BLOCKS_PER_CU)
     walk_kernel(const typename std::conditional<F64, WalkArgsF64, WalkArgsF32>::type A)
 {
-    walk_body<F64, KAHAN, ADJ, false>(A);
+    walk_body<F64, KAHAN, ADJ, false, GEN>(A);
 }
 
-template <bool F64, bool KAHAN>
-__global__ void __launch_bounds__(256) batch_walk_kernel(const BatchArgs A)
+template <bool F64, bool KAHAN, bool GEN>
+__global__ void __launch_bounds__(256, F64 ? FK_BATCH_F64_BLOCKS_PER_CU : FK_BATCH_F32_BLOCKS_PER_CU)
+    batch_walk_kernel(const BatchArgs A)
 {
-    walk_body<F64, KAHAN, false, true>(A);
+    walk_body<F64, KAHAN, false, true, GEN>(A);
 }
 
 }  // namespace
@@ -542,12 +681,54 @@ hipError_t launch_zero_queue(unsigned long long* queue, hipStream_t stream)
     return hipGetLastError();
 }
 
+namespace {
+
+bool general(const WalkCommon& c) { return c.domain == FK_DOMAIN_BALL || c.exit_rule == FK_EXIT_BRIDGE; }
+
+template <bool F64, bool KAHAN, bool ADJ, class A>
+void launch_walk(const A& a, const LaunchCfg& cfg, hipStream_t stream)
+{
+    if (general(a.c))
+        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+    else
+        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+}
+
+template <bool GEN>
+const void* walk_fn(int precision)
+{
+    return precision == FK_F64 ? (const void*)walk_kernel<true, false, false, GEN>
+         : precision == FK_MIXED_KAHAN ? (const void*)walk_kernel<false, true, false, GEN>
+                                       : (const void*)walk_kernel<false, false, false, GEN>;
+}
+
+template <bool GEN>
+const void* batch_fn(int precision)
+{
+    return precision == FK_F64 ? (const void*)batch_walk_kernel<true, false, GEN>
+         : precision == FK_MIXED_KAHAN ? (const void*)batch_walk_kernel<false, true, GEN>
+                                       : (const void*)batch_walk_kernel<false, false, GEN>;
+}
+
+template <bool GEN>
+void launch_batch(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream)
+{
+    if (a.precision == FK_F64)
+        hipLaunchKernelGGL((batch_walk_kernel<true, false, GEN>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+    else if (a.precision == FK_MIXED_KAHAN)
+        hipLaunchKernelGGL((batch_walk_kernel<false, true, GEN>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+    else
+        hipLaunchKernelGGL((batch_walk_kernel<false, false, GEN>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+}
+
+}  // namespace
+
 hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream_t stream, bool adjoint)
 {
     if (adjoint)
-        hipLaunchKernelGGL((walk_kernel<true, false, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+        launch_walk<true, false, true>(a, cfg, stream);
     else
-        hipLaunchKernelGGL((walk_kernel<true, false, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+        launch_walk<true, false, false>(a, cfg, stream);
     return hipGetLastError();
 }
 
@@ -555,42 +736,36 @@ hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cf
 {
     if (adjoint) {
         if (kahan)
-            hipLaunchKernelGGL((walk_kernel<false, true, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+            launch_walk<false, true, true>(a, cfg, stream);
         else
-            hipLaunchKernelGGL((walk_kernel<false, false, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+            launch_walk<false, false, true>(a, cfg, stream);
     } else {
         if (kahan)
-            hipLaunchKernelGGL((walk_kernel<false, true, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+            launch_walk<false, true, false>(a, cfg, stream);
         else
-            hipLaunchKernelGGL((walk_kernel<false, false, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+            launch_walk<false, false, false>(a, cfg, stream);
     }
     return hipGetLastError();
 }
 
-hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu)
+hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, bool gen)
 {
-    const void* fn = precision == FK_F64 ? (const void*)walk_kernel<true, false, false>
-                   : precision == FK_MIXED_KAHAN ? (const void*)walk_kernel<false, true, false>
-                                                 : (const void*)walk_kernel<false, false, false>;
+    const void* fn = gen ? walk_fn<true>(precision) : walk_fn<false>(precision);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
-hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream)
+hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, bool gen)
 {
-    if (a.precision == FK_F64)
-        hipLaunchKernelGGL((batch_walk_kernel<true, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
-    else if (a.precision == FK_MIXED_KAHAN)
-        hipLaunchKernelGGL((batch_walk_kernel<false, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+    if (gen)
+        launch_batch<true>(a, cfg, stream);
     else
-        hipLaunchKernelGGL((batch_walk_kernel<false, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+        launch_batch<false>(a, cfg, stream);
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu)
+hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, bool gen)
 {
-    const void* fn = precision == FK_F64 ? (const void*)batch_walk_kernel<true, false>
-                   : precision == FK_MIXED_KAHAN ? (const void*)batch_walk_kernel<false, true>
-                                                 : (const void*)batch_walk_kernel<false, false>;
+    const void* fn = gen ? batch_fn<true>(precision) : batch_fn<false>(precision);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 

@@ -56,7 +56,7 @@ class fk_boundary(C.Structure):
 class fk_params(C.Structure):
     _fields_ = [("paths_per_station", C.c_int64), ("dt", C.c_double), ("seed", C.c_uint64), ("G", C.c_double),
                 ("h", C.c_double), ("precision", C.c_int32), ("exit_rule", C.c_int32), ("pairing", C.c_int32),
-                ("strict", C.c_int32), ("max_steps", C.c_int64), ("problem_id", C.c_uint32), ("pad0", C.c_uint32),
+                ("strict", C.c_int32), ("max_steps", C.c_int64), ("problem_id", C.c_uint32), ("domain", C.c_int32),
                 ("path_offset", C.c_int64)]
 
 
@@ -357,6 +357,7 @@ def make_params(prob, **over) -> fk_params:
     p.strict = 0
     p.max_steps = int(g("max_steps", (1 << 31) - 1))
     p.problem_id = int(g("problem_id", 0))
+    p.domain = int(g("domain", 0))
     p.path_offset = int(g("path_offset", 0))
     return p
 

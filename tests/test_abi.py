@@ -100,7 +100,8 @@ def _call(box, src, bc, prm, n_stations=8, ws_bytes=None, stations=1, out=1, ws=
 @host_only
 @pytest.mark.parametrize("field,value,status", [
     ("dt", 0.0, F.FK_EINVAL), ("dt", float("nan"), F.FK_EINVAL), ("paths_per_station", 1, F.FK_EINVAL),
-    ("precision", 3, F.FK_EINVAL), ("exit_rule", 2, F.FK_EINVAL), ("pairing", 5, F.FK_EINVAL),
+    ("precision", 3, F.FK_EINVAL), ("exit_rule", 3, F.FK_EINVAL), ("pairing", 5, F.FK_EINVAL),
+    ("domain", 2, F.FK_EINVAL),
     ("max_steps", 0, F.FK_EINVAL), ("G", float("inf"), F.FK_EINVAL), ("h", -1.0, F.FK_EINVAL),
     ("path_offset", (1 << 32) - 50, F.FK_EUNSUPPORTED),
 ])
@@ -109,6 +110,20 @@ def test_bad_params_rejected(field, value, status):
     setattr(prm, field, value)
     assert _call(box, src, bc, prm, ws_bytes=1 << 30) == status
     assert F.lib().fk_last_error().decode() != ""
+
+
+@host_only
+@host_only
+def test_ball_and_bridge_arguments_rejected():
+    pr, box, src, bc, prm, keep = _host_problem()
+    prm.domain = 1                      # a ball needs a cubic box
+    box.hi[0] = box.hi[0] + 0.5
+    assert _call(box, src, bc, prm) == F.FK_EINVAL
+    box.hi[0] = box.hi[0] - 0.5
+    prm.domain = 0
+    prm.exit_rule = 2                   # bridge: max_steps <= 2^30
+    prm.max_steps = (1 << 30) + 1
+    assert _call(box, src, bc, prm) == F.FK_EUNSUPPORTED
 
 
 @host_only
