@@ -11,11 +11,13 @@ sqrt(dt) = 2 m, FP64.  Inputs live in device memory before timing starts.
 Prints one JSON line: Brownian steps per second of the whole job (exact
 in-kernel step counts over the event-timed region), the ALU roofline of the
 walk kernel, station estimates per second at fixed relative standard error,
-the mixed-precision kernel on the same workload, and the CPU oracle timed on
-a bounded sample on the host.
+the mixed-precision kernel on the same workload, the paper's Table 1
+workload (its experiment 1 at every time step and walk count, next to the
+K20Xm times it reports), and the CPU oracle timed on a bounded sample on the
+host.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64|mixed]
-                  [--no-cpu-baseline] [--cpu-seconds S]
+                  [--no-cpu-baseline] [--cpu-seconds S] [--no-paper-table]
 """
 from __future__ import annotations
 
@@ -124,7 +126,64 @@ def cpu_baseline(prob, seconds):
             "sample": f"all {S} stations x first {n} walks, u and g_z (FP64): {steps} steps in {elapsed:.1f} s"}
 
 
-def run(precision_name, K, Wm, cpu_seconds, want_cpu):
+# The paper's Table 1: seconds on one Tesla K20Xm for experiment 1 (31
+# stations, potential) at its time steps Delta t and walk counts N.  Lengths
+# are read as km (the only unit that makes these times consistent with the
+# expected exit time of the 10 km ball).
+PAPER_TABLE1_N = (1024, 2048, 4096, 5120, 10240, 20480, 40960, 51200)
+PAPER_TABLE1_S = {
+    0.1: (0.3, 0.4, 0.4, 0.4, 0.5, 0.5, 0.9, 1.1),
+    0.05: (0.8, 0.9, 1.0, 1.0, 1.1, 1.2, 2.0, 2.5),
+    0.01: (4.8, 5.3, 5.8, 5.9, 6.4, 7.1, 11.5, 14.3),
+    0.005: (9.9, 10.9, 12.2, 12.3, 13.0, 14.7, 24.1, 29.4),
+    0.001: (52.8, 55.6, 59.6, 61.1, 65.7, 75.8, 125.6, 155.7),
+}
+
+
+def paper_table1(precision_name):
+    """Experiment 1 of the paper (ball of radius 10 km, zero data, 100 m cube,
+    31 stations) at every cell of Table 1: seconds per solve on this GPU
+    (event-timed, median of 3, inputs resident) next to the K20Xm's."""
+    import numpy as np
+    import torch
+
+    from paper_1709_07469_amd import fkgrav as F
+    from paper_1709_07469_amd import workloads as W
+
+    prec = W.PREC_F64 if precision_name == "f64" else W.PREC_MIXED_F64ACC
+    rows, ours_total, paper_total, steps_total = [], 0.0, 0.0, 0
+    for dtp, paper_s in PAPER_TABLE1_S.items():
+        row = []
+        for N, ps in zip(PAPER_TABLE1_N, paper_s):
+            prob = W.paper_ball(dt_paper=dtp, paths_per_station=N, precision=prec)
+            P = F.Prepared(prob)
+            ws = F.alloc_workspace(F.fk_workspace_bytes(0, prob.n_stations, P.params))
+            out = F.alloc_stats(prob.n_stations)
+            F.fk_solve_potential(P.stations, P.box, P.source, P.bc, P.params, out, ws)
+            times = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                F.fk_solve_potential(P.stations, P.box, P.source, P.bc, P.params, out, ws)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1) / 1e3)
+            t = float(np.median(times))
+            st = F.stats_to_numpy(out)[: prob.n_stations]
+            steps_total += int(st["sum_steps"].sum())
+            ours_total += t
+            paper_total += ps
+            row.append(round(t, 5))
+        rows.append({"dt_paper": dtp, "seconds": row, "paper_k20xm_seconds": list(paper_s)})
+    return {"workload": "paper experiment 1: ball R = 10 km (lengths in km), zero data, cube [0,100 m]^3 of "
+                        "2000 kg/m^3, 31 stations y = 50 m, z = 200 m, x = -100..200 m; potential",
+            "precision": precision_name, "N": list(PAPER_TABLE1_N), "rows": rows,
+            "total_seconds": ours_total, "paper_total_seconds": paper_total,
+            "speedup_vs_paper_total": paper_total / ours_total, "steps": steps_total,
+            "steps_per_s": steps_total / ours_total}
+
+
+def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True):
     import numpy as np
     import torch
 
@@ -219,6 +278,8 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu):
         result["mixed"] = {"value": mval, "unit": "Brownian steps/s", "speedup_vs_f64": mval / value,
                            "max_abs_diff_vs_f64_in_combined_se": {"u": du, "g_z": dg}}
 
+    if want_paper:
+        result["paper_table1"] = paper_table1(precision_name)
     if want_cpu:
         result["cpu_baseline"] = cpu_baseline(prob, cpu_seconds)
     return result
@@ -231,6 +292,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["f64", "mixed"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper-table", action="store_true", help="skip the paper's Table 1 workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this many bytes (calibrates HBM byte counters)")
@@ -244,7 +306,8 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr, flush=True)
         sys.exit(1)
     torch.cuda.set_device(0)
-    res = run(a.precision, max(1, a.steps), max(0, a.warmup), a.cpu_seconds, not a.no_cpu_baseline)
+    res = run(a.precision, max(1, a.steps), max(0, a.warmup), a.cpu_seconds, not a.no_cpu_baseline,
+              not a.no_paper_table)
     if a.copy_bytes > 0:
         src = torch.ones(a.copy_bytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
