@@ -56,7 +56,11 @@ ISSUE_COST = {"philox_block": 64.21, "box_muller_pair_f64": 119.88, "box_muller_
 # over the u and g_z launches), each scaled by what the same counter reads for
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
-PMC_BYTES = None
+PMC_BYTES = {
+    "sources_sha256": "0f6ce832e9fe9d6efbed3c94593173d64b2b0c073cd2cb57a5646e093f3ff107",
+    "fetch_scale": 1.999913696198699, "write_scale": 1.0,
+    "f64": {"fetch_kib": 17722.875, "write_kib": 487316.546875},
+}
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")
 
