@@ -6,7 +6,9 @@ potential u and the vertical acceleration g_z (common-random-number central
 difference) at all 64 stations of the SI-prism workload -- box
 [0,1000]^2 x [-500,100] m, one prism [400,600]x[450,550]x[-300,-150] m of
 300 kg/m^3, exact prism data on the faces, 1e5 walks per station,
-sqrt(dt) = 2 m, FP64.  Inputs live in device memory before timing starts.
+sqrt(dt) = 2 m, FP64 -- by default as one persistent launch over both
+(--launch separate: two launches).  Inputs live in device memory before
+timing starts.
 
 Prints one JSON line: Brownian steps per second of the whole job (exact
 in-kernel step counts over the event-timed region), the ALU roofline of the
@@ -17,7 +19,8 @@ K20Xm times it reports), and the CPU oracle timed on a bounded sample on the
 host.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64|mixed]
-                  [--no-cpu-baseline] [--cpu-seconds S] [--no-paper-table]
+                  [--launch batched|separate] [--no-cpu-baseline] [--cpu-seconds S]
+                  [--no-paper-table]
 """
 from __future__ import annotations
 
@@ -48,8 +51,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 64.21, "box_muller_pair_f64": 119.88, "box_muller_pair_f32": 20.36,
-              "step_f64": 29.41, "step_f32_f64sum": 25.07}
+ISSUE_COST = {"philox_block": 62.39, "box_muller_pair_f64": 93.58, "box_muller_pair_f32": 20.33,
+              "step_f64": 29.45, "step_f32_f64sum": 24.99}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -59,7 +62,7 @@ ISSUE_COST = {"philox_block": 64.21, "box_muller_pair_f64": 119.88, "box_muller_
 PMC_BYTES = {
     "sources_sha256": "0f6ce832e9fe9d6efbed3c94593173d64b2b0c073cd2cb57a5646e093f3ff107",
     "fetch_scale": 1.999913696198699, "write_scale": 1.0,
-    "f64": {"fetch_kib": 17722.875, "write_kib": 487316.546875},
+    "f64_separate": {"fetch_kib": 17722.875, "write_kib": 487316.546875},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")
@@ -85,12 +88,13 @@ def sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision: str):
+def measured_traffic(precision: str, mode: str):
     """HBM bytes per walk-kernel launch from the recorded counters, or None
-    when they were taken on other kernel sources."""
-    if not PMC_BYTES or PMC_BYTES.get("sources_sha256") != sources_sha256() or precision not in PMC_BYTES:
+    when they were taken on other kernel sources or another launch form."""
+    key = precision + "_" + mode
+    if not PMC_BYTES or PMC_BYTES.get("sources_sha256") != sources_sha256() or key not in PMC_BYTES:
         return None
-    r = PMC_BYTES[precision]
+    r = PMC_BYTES[key]
     return r["fetch_kib"] * 1024 * PMC_BYTES["fetch_scale"] + r["write_kib"] * 1024 * PMC_BYTES["write_scale"]
 
 
@@ -187,54 +191,92 @@ def paper_table1(precision_name):
             "steps_per_s": steps_total / ours_total}
 
 
-def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True):
-    import numpy as np
-    import torch
-
+def make_stepper(prob, mode):
+    """One pass of the hot path over the benchmark problem: u and g_z at all
+    stations, either as two launches (mode "separate") or as one persistent
+    launch over both (mode "batched").  Returns (step, stats) where stats()
+    gives the u and g_z station statistics of the last pass."""
     from paper_1709_07469_amd import fkgrav as F
-    from paper_1709_07469_amd import workloads as W
 
-    prec = W.PREC_F64 if precision_name == "f64" else W.PREC_MIXED_F64ACC
-    prob = W.cfg2(precision=prec)
     S = prob.n_stations
+    if mode == "batched":
+        PB = F.PreparedBatch([prob, prob], [0, 1])
+        ws = F.alloc_workspace(F.fk_batch_workspace_bytes(PB.problems))
+        out = F.alloc_stats(PB.n_out)
+
+        def step():
+            F.fk_solve_batch(PB.problems, out, ws)
+
+        def stats():
+            st = F.stats_to_numpy(out)
+            return st[:S], st[S:2 * S]
+        return step, stats
     P = F.Prepared(prob)
     ws_u = F.alloc_workspace(F.fk_workspace_bytes(0, S, P.params))
     ws_g = F.alloc_workspace(F.fk_workspace_bytes(1, S, P.params))
     out_u, out_g = F.alloc_stats(S), F.alloc_stats(S)
 
-    def step(params):
-        F.fk_solve_potential(P.stations, P.box, P.source, P.bc, params, out_u, ws_u)
-        F.fk_solve_gz(P.stations, P.box, P.source, P.bc, params, out_g, ws_g)
+    def step():
+        F.fk_solve_potential(P.stations, P.box, P.source, P.bc, P.params, out_u, ws_u)
+        F.fk_solve_gz(P.stations, P.box, P.source, P.bc, P.params, out_g, ws_g)
 
+    def stats():
+        return F.stats_to_numpy(out_u)[:S], F.stats_to_numpy(out_g)[:S]
+    return step, stats
+
+
+def timed(step, K, Wm, walk_timing=False):
+    """Wm untimed passes, then K passes between two events; returns seconds
+    and (optionally) the walk kernels' own event times in ms."""
+    import torch
+
+    from paper_1709_07469_amd import fkgrav as F
     for _ in range(Wm):
-        step(P.params)
+        step()
     torch.cuda.synchronize()
-    F.fk_timing_read()
-    F.fk_timing_enable(True)
+    if walk_timing:
+        F.fk_timing_read()
+        F.fk_timing_enable(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
     for _ in range(K):
-        step(P.params)
+        step()
     e1.record()
     torch.cuda.synchronize()
-    F.fk_timing_enable(False)
-    walk_ms = F.fk_timing_read()
-    elapsed = e0.elapsed_time(e1) / 1e3
-    su, sg = F.stats_to_numpy(out_u)[:S], F.stats_to_numpy(out_g)[:S]
+    walk_ms = None
+    if walk_timing:
+        F.fk_timing_enable(False)
+        walk_ms = F.fk_timing_read()
+    return e0.elapsed_time(e1) / 1e3, walk_ms
+
+
+def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="batched"):
+    import numpy as np
+
+    from paper_1709_07469_amd import workloads as W
+
+    prec = W.PREC_F64 if precision_name == "f64" else W.PREC_MIXED_F64ACC
+    prob = W.cfg2(precision=prec)
+    S = prob.n_stations
+    step, stats = make_stepper(prob, mode)
+    elapsed, walk_ms = timed(step, K, Wm, walk_timing=True)
+    su, sg = stats()
     steps_per_pass = int(su["sum_steps"].sum()) + int(sg["sum_steps"].sum())
     value = steps_per_pass * K / elapsed
 
     ops = algorithmic_ops_per_step(precision_name)
     achieved = steps_per_pass * K * ops / (sum(walk_ms) * 1e-3) / 1e12
     peak = PEAK_LANE_OPS / 1e12
-    walks_per_launch = S * prob.paths_per_station * 1.5          # u: S*N walks, g_z: 2*S*N
+    launches_per_pass = len(walk_ms) // K
+    walks_per_launch = 3 * S * prob.paths_per_station / launches_per_pass   # u: S*N walks, g_z: 2*S*N
     algo_bytes = walks_per_launch * (32 + 4)                     # exit record + step count per walk
-    traffic = measured_traffic(precision_name)
+    traffic = measured_traffic(precision_name, mode)
+    kname = "walk_kernel" if mode == "separate" else "batch_walk_kernel"
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "T lane-slots/s", "frac": achieved / peak,
             "traffic": traffic,
-            "kernel": "walk_kernel<F64>" if precision_name == "f64" else "walk_kernel<F32, F64 sum>",
-            "ops_per_step": ops, "steps_per_launch": steps_per_pass / 2,
+            "kernel": kname + ("<F64>" if precision_name == "f64" else "<F32, F64 sum>"),
+            "ops_per_step": ops, "steps_per_launch": steps_per_pass / launches_per_pass,
             "kernel_avg_ms": float(np.mean(walk_ms)), "launches": len(walk_ms),
             "kernel_share_of_step": sum(walk_ms) / (elapsed * 1e3),
             "algorithmic_bytes_per_launch": algo_bytes,
@@ -252,34 +294,31 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True):
         "config": {"workload": "SI prism 300 kg/m^3 in box [0,1000]^2x[-500,100] m, 8x8 stations at z=0, "
                                "1e5 walks/station, sqrt(dt)=2 m, exact prism data, u + g_z (CRN, h=2 m)",
                    "stations": S, "paths_per_station": prob.paths_per_station, "dt": prob.dt,
-                   "precision": precision_name, "steps_per_pass": steps_per_pass},
+                   "precision": precision_name, "launch": mode, "steps_per_pass": steps_per_pass},
         "roofline": roof,
         "station_estimates_per_s": est,
     }
 
     if precision_name == "f64":
-        # the mixed-precision kernel on the same workload, outside the timed region
-        pm = F.make_params(prob, precision=W.PREC_MIXED_F64ACC)
-        out_u2, out_g2 = F.alloc_stats(S), F.alloc_stats(S)
-        F.fk_solve_potential(P.stations, P.box, P.source, P.bc, pm, out_u2, ws_u)
-        F.fk_solve_gz(P.stations, P.box, P.source, P.bc, pm, out_g2, ws_g)
-        torch.cuda.synchronize()
-        m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        m0.record()
-        for _ in range(K):
-            F.fk_solve_potential(P.stations, P.box, P.source, P.bc, pm, out_u2, ws_u)
-            F.fk_solve_gz(P.stations, P.box, P.source, P.bc, pm, out_g2, ws_g)
-        m1.record()
-        torch.cuda.synchronize()
-        mu, mg = F.stats_to_numpy(out_u2)[:S], F.stats_to_numpy(out_g2)[:S]
+        # the same pass in the other launch form, and the mixed-precision
+        # kernel (its faster form: two launches) -- outside the timed region
+        other = "separate" if mode == "batched" else "batched"
+        ostep, ostats = make_stepper(prob, other)
+        oel, _ = timed(ostep, K, 1)
+        result["f64_" + other] = {"value": steps_per_pass * K / oel, "unit": "Brownian steps/s"}
+        pmix = prob.replace(precision=W.PREC_MIXED_F64ACC)
+        mstep, mstats = make_stepper(pmix, "separate")
+        mel, _ = timed(mstep, K, 1)
+        mu, mg = mstats()
         msteps = int(mu["sum_steps"].sum()) + int(mg["sum_steps"].sum())
-        mval = msteps * K / (m0.elapsed_time(m1) / 1e3)
+        mval = msteps * K / mel
         # the two kernels draw different normals (FP32 and FP64 streams), so
         # their estimates are independent: differences are scaled by the
         # standard error of the difference, sqrt(se_a^2 + se_b^2)
         du = float(np.max(np.abs(mu["mean"] - su["mean"]) / np.hypot(mu["se"], su["se"])))
         dg = float(np.max(np.abs(mg["mean"] - sg["mean"]) / np.hypot(mg["se"], sg["se"])))
-        result["mixed"] = {"value": mval, "unit": "Brownian steps/s", "speedup_vs_f64": mval / value,
+        result["mixed"] = {"value": mval, "unit": "Brownian steps/s", "launch": "separate",
+                           "speedup_vs_f64": mval / value,
                            "max_abs_diff_vs_f64_in_combined_se": {"u": du, "g_z": dg}}
 
     if want_paper:
@@ -295,6 +334,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", choices=["f64", "mixed"], default="f64")
+    ap.add_argument("--launch", choices=["batched", "separate"], default="batched",
+                    help="u and g_z in one persistent launch (default) or in two")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-table", action="store_true", help="skip the paper's Table 1 workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -311,7 +352,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     res = run(a.precision, max(1, a.steps), max(0, a.warmup), a.cpu_seconds, not a.no_cpu_baseline,
-              not a.no_paper_table)
+              not a.no_paper_table, a.launch)
     if a.copy_bytes > 0:
         src = torch.ones(a.copy_bytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -140,18 +140,106 @@ __device__ __forceinline__ void sincos_2pi(double u, double& s, double& c)
     c = ((qi + 1) & 2) ? -cc : cc;
 }
 
+// Tables that shorten the two FP64 transcendentals of the walk loop, held in
+// LDS and filled at the start of every launch by the table-free routines
+// above (so they carry those routines' ~1 ulp accuracy):
+//   sc[k] = (sin, cos)(2 pi k / 256), k = 0..255;
+//   lg[j] = (v, -ln v) with v = 1/c rounded, c = 1 + (j - 37)/128, j = 0..90,
+//           the grid of c over [sqrt(1/2), sqrt(2)).
+struct BmTables {
+    static constexpr int kSc = 256;
+    static constexpr int kLg = 91;
+    static constexpr int kLgOff = 37;
+    double2 sc[kSc];
+    double2 lg[kLg];
+};
+
+// The block's table, in LDS (one instance per kernel that uses it).
+__device__ __forceinline__ BmTables* bm_tables()
+{
+    __shared__ BmTables t;
+    return &t;
+}
+
+// Fills T with every thread of the block; ends with a block barrier.
+__device__ __forceinline__ void fill_bm_tables(BmTables& T)
+{
+    for (int i = threadIdx.x; i < BmTables::kSc + BmTables::kLg; i += blockDim.x) {
+        if (i < BmTables::kSc) {
+            double s, c;
+            sincos_2pi((double)i * (1.0 / BmTables::kSc), s, c);
+            T.sc[i] = make_double2(s, c);
+        } else {
+            const int j = i - BmTables::kSc;
+            const double v = 1.0 / (1.0 + (double)(j - BmTables::kLgOff) * (1.0 / 128.0));
+            T.lg[j] = make_double2(v, 0.5 * neg2_log(v));
+        }
+    }
+    __syncthreads();
+}
+
+// -2 ln u for u in (0, 1] with the table: u = m 2^e, m in [sqrt(1/2),
+// sqrt(2)); c = 1 + j/128 the nearest grid point, v = 1/c rounded; then
+// ln m = -ln v + ln(1 + r) with r = m v - 1 (one rounding, |r| < 0.0056), and
+// ln(1 + r) is its series to r^8 (truncation below 1e-19 relative).  Near
+// u = 1 the grid point is c = v = 1 and r = m - 1 exactly.
+__device__ __forceinline__ double neg2_log_t(double u, const BmTables& T)
+{
+    double m = __builtin_amdgcn_frexp_mant(u);   // [0.5, 1)
+    int e = __builtin_amdgcn_frexp_exp(u);
+    if (m < 0x1.6a09e667f3bcdp-1) {
+        m = 2.0 * m;
+        e -= 1;
+    }
+    const int j = (int)__builtin_rint(fma(m, 128.0, -128.0)) + BmTables::kLgOff;
+    const double2 g = T.lg[j];
+    const double r = fma(m, g.x, -1.0);
+    double p = -0x1.0000000000000p-3;            // -1/8
+    p = fma(p, r, 0x1.2492492492492p-3);         // 1/7
+    p = fma(p, r, -0x1.5555555555555p-3);        // -1/6
+    p = fma(p, r, 0x1.999999999999ap-3);         // 1/5
+    p = fma(p, r, -0x1.0000000000000p-2);        // -1/4
+    p = fma(p, r, 0x1.5555555555555p-2);         // 1/3
+    p = fma(p, r, -0.5);
+    const double l1p = fma(p, r * r, r);         // ln(1 + r)
+    const double fe = -2.0 * (double)e;
+    return fma(fe, 0x1.62e42fee00000p-1, fma(fe, 0x1.a39ef35793c76p-33, -2.0 * (g.y + l1p)));
+}
+
+// sin and cos of 2 pi u, u in (0, 1], with the table: k = nearest integer
+// to 256 u, t = u - k/256 (exact, |t| <= 1/512), theta = 2 pi t; sin and cos
+// of theta by their series to theta^7 and theta^8 (truncation below 1e-20),
+// rotated by the table's angle 2 pi k / 256.
+__device__ __forceinline__ void sincos_2pi_t(double u, const BmTables& T, double& s, double& c)
+{
+    const double q = __builtin_rint(256.0 * u);
+    const double t = fma(-q, 1.0 / 256.0, u);
+    const double th = t * 0x1.921fb54442d18p+2;  // 2 pi
+    const double z = th * th;
+    double ps = fma(-0x1.a01a01a01a01ap-13, z, 0x1.1111111111111p-7);   // -1/5040, 1/120
+    ps = fma(ps, z, -0x1.5555555555555p-3);                              // -1/6
+    const double st = fma(th * z, ps, th);
+    double pc = fma(0x1.a01a01a01a01ap-16, z, -0x1.6c16c16c16c17p-10);  // 1/40320, -1/720
+    pc = fma(pc, z, 0x1.5555555555555p-5);                               // 1/24
+    pc = fma(pc, z, -0.5);
+    const double ct = fma(pc, z, 1.0);
+    const double2 a = T.sc[(int)q & (BmTables::kSc - 1)];
+    s = fma(a.x, ct, a.y * st);
+    c = fma(a.y, ct, -(a.x * st));
+}
+
 // FP64 stream: one block -> two 53-bit uniforms in (0, 1] -> one Box-Muller
 // pair (cosine branch first): z0 = R cos(2 pi U2), z1 = R sin(2 pi U2),
 // R = sqrt(-2 ln U1).
-__device__ __forceinline__ void normals_f64(const Block& b, double& z0, double& z1)
+__device__ __forceinline__ void normals_f64(const Block& b, const BmTables& T, double& z0, double& z1)
 {
     const uint64_t a = ((((uint64_t)b.w1) << 21) | (uint64_t)(b.w0 >> 11)) + 1ull;
     const uint64_t c = ((((uint64_t)b.w3) << 21) | (uint64_t)(b.w2 >> 11)) + 1ull;
     const double u1 = (double)a * 0x1p-53;
     const double u2 = (double)c * 0x1p-53;
-    const double r = sqrt_nonneg(neg2_log(u1));
+    const double r = sqrt_nonneg(neg2_log_t(u1, T));
     double s, co;
-    sincos_2pi(u2, s, co);
+    sincos_2pi_t(u2, T, s, co);
     z0 = r * co;
     z1 = r * s;
 }

@@ -61,6 +61,8 @@ __global__ void __launch_bounds__(256) philox_probe(uint32_t* out, uint32_t seed
 // previous normals (2-3 extra integer ops per pair, included in the cost).
 __global__ void __launch_bounds__(256) bm64_probe(uint32_t* out, uint32_t seed)
 {
+    fk::BmTables* tab = fk::bm_tables();
+    fk::fill_bm_tables(*tab);
     uint32_t w[kChains][4];
     for (int j = 0; j < kChains; ++j) {
         w[j][0] = threadIdx.x * 2654435761u + j;
@@ -72,7 +74,7 @@ __global__ void __launch_bounds__(256) bm64_probe(uint32_t* out, uint32_t seed)
 #pragma unroll
         for (int j = 0; j < kChains; ++j) {
             double z0, z1;
-            fk::normals_f64(fk::Block{w[j][0], w[j][1], w[j][2], w[j][3]}, z0, z1);
+            fk::normals_f64(fk::Block{w[j][0], w[j][1], w[j][2], w[j][3]}, *tab, z0, z1);
             const uint64_t a = (uint64_t)__double_as_longlong(z0), b = (uint64_t)__double_as_longlong(z1);
             w[j][0] = (uint32_t)a;
             w[j][1] = (uint32_t)(a >> 32) ^ (uint32_t)b;

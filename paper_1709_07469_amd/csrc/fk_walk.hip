@@ -196,7 +196,7 @@ struct Prec<true> {
     using Src = SourceF64;
     static constexpr int kNormals = 2;   // per Philox block
     static constexpr int kMacro = 2;     // steps per 3 blocks
-    __device__ static void normals(const Block& b, T* z) { normals_f64(b, z[0], z[1]); }
+    __device__ static void normals(const Block& b, T* z, const BmTables* t) { normals_f64(b, *t, z[0], z[1]); }
     __device__ static T fmat(T a, T b, T c) { return fma(a, b, c); }
     __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f64(s, x, y, z); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f64(s, x, y, z); }
@@ -222,7 +222,7 @@ struct Prec<false> {
     using Src = SourceF32;
     static constexpr int kNormals = 4;
     static constexpr int kMacro = 4;
-    __device__ static void normals(const Block& b, T* z)
+    __device__ static void normals(const Block& b, T* z, const BmTables*)
     {
         normals_f32(b.w0, b.w1, z[0], z[1]);
         normals_f32(b.w2, b.w3, z[2], z[3]);
@@ -472,6 +472,12 @@ __device__ __forceinline__ void walk_body(const Args& A)
 
     __shared__ int tail_lane[kMaxWaves][64];
     __shared__ T tail_z[kMaxWaves][3 * 64][NPB];
+    const BmTables* bmt = nullptr;
+    if constexpr (F64) {
+        BmTables* t = bm_tables();
+        fill_bm_tables(*t);
+        bmt = t;
+    }
 
     Queue Q;
     LaneProblem<F64> P;
@@ -590,7 +596,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
                 if (r < B) {
                     const Block bl = philox10(ks + (uint32_t)r, ps, ss, pid, key0, key1);
                     T z[NPB];
-                    Prec<F64>::normals(bl, z);
+                    Prec<F64>::normals(bl, z, bmt);
 #pragma unroll
                     for (int j = 0; j < NPB; ++j) tail_z[wave][g][j] = z[j];
                 }
@@ -628,7 +634,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             const Block bl = philox10(W.k + b, W.pctr, W.sctr, P.pid, P.key0, P.key1);
-            Prec<F64>::normals(bl, z + NPB * b);
+            Prec<F64>::normals(bl, z + NPB * b, bmt);
         }
         W.k += 3;
         bool done = false;
@@ -777,6 +783,8 @@ namespace {
 __global__ void stream_blocks_kernel(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
                                      double* z64, float* z32)
 {
+    BmTables* bmt = bm_tables();
+    fill_bm_tables(*bmt);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const Block b = philox10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], key0, key1);
@@ -786,7 +794,7 @@ __global__ void stream_blocks_kernel(const uint32_t* ctr, int64_t n, uint32_t ke
         words[4 * i + 2] = b.w2;
         words[4 * i + 3] = b.w3;
     }
-    if (z64) normals_f64(b, z64[2 * i], z64[2 * i + 1]);
+    if (z64) normals_f64(b, *bmt, z64[2 * i], z64[2 * i + 1]);
     if (z32) {
         normals_f32(b.w0, b.w1, z32[4 * i], z32[4 * i + 1]);
         normals_f32(b.w2, b.w3, z32[4 * i + 2], z32[4 * i + 3]);
