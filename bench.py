@@ -51,8 +51,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 62.39, "box_muller_pair_f64": 93.58, "box_muller_pair_f32": 20.33,
-              "step_f64": 29.45, "step_f32_f64sum": 24.99}
+ISSUE_COST = {"philox_block": 62.91, "box_muller_pair_f64": 94.30, "box_muller_pair_f32": 20.48,
+              "step_f64": 29.40, "step_f32_f64sum": 25.02}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -60,9 +60,10 @@ ISSUE_COST = {"philox_block": 62.39, "box_muller_pair_f64": 93.58, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "0f6ce832e9fe9d6efbed3c94593173d64b2b0c073cd2cb57a5646e093f3ff107",
-    "fetch_scale": 1.999913696198699, "write_scale": 1.0,
-    "f64_separate": {"fetch_kib": 17722.875, "write_kib": 487316.546875},
+    "sources_sha256": "db727111cc75d50ede5d9981815b163afde21b59549cfe82fce1fb03b7099c8d",
+    "fetch_scale": 1.9998838968923347, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 197.75, "write_kib": 890324.90625},
+    "f64_separate": {"fetch_kib": 220.59375, "write_kib": 438656.40625},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")
