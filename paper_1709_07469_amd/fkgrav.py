@@ -25,10 +25,12 @@ LIB_PATH = os.environ.get("FKGRAV_LIB") or os.path.join(_PKG, "libfkgrav.so")
 
 FK_OK, FK_EINVAL, FK_EDOMAIN, FK_EWORKSPACE, FK_EDEVICE, FK_ETRUNC, FK_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FK_F64, FK_MIXED_F64ACC, FK_MIXED_KAHAN = 0, 1, 2
-FK_EXIT_OVERSHOOT, FK_EXIT_INTERSECT = 0, 1
+FK_EXIT_OVERSHOOT, FK_EXIT_INTERSECT, FK_EXIT_BRIDGE = 0, 1, 2
+FK_DOMAIN_BOX, FK_DOMAIN_BALL = 0, 1
 FK_BC_ZERO, FK_BC_QUADRATIC, FK_BC_POINT_MASSES, FK_BC_PRISMS, FK_BC_FACE_GRID = 0, 1, 2, 3, 4
 FK_PAIR_CRN, FK_PAIR_INDEPENDENT = 0, 1
 FK_MAX_PRISMS = FK_MAX_SPHERES = FK_MAX_BC_ITEMS = 16
+FK_MAX_BATCH = 256
 CAP_FLAG = 0x80000000
 
 

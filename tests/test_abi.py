@@ -43,6 +43,21 @@ def test_header_functions_are_exported():
         assert hasattr(L, n), n
 
 
+def test_enum_values_match_the_binding():
+    # every enumerator of the header has the binding's value (and the
+    # workload module's, where it names one)
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    found = dict((k, int(v)) for k, v in re.findall(r"\b(FK_[A-Z0-9_]+)\s*=\s*(-?\d+)", text))
+    assert len(found) >= 25
+    for name, value in found.items():
+        assert getattr(F, name) == value, name
+    assert (W.EXIT_OVERSHOOT, W.EXIT_INTERSECT, W.EXIT_BRIDGE) == (F.FK_EXIT_OVERSHOOT, F.FK_EXIT_INTERSECT,
+                                                                   F.FK_EXIT_BRIDGE)
+    assert (W.DOMAIN_BOX, W.DOMAIN_BALL) == (F.FK_DOMAIN_BOX, F.FK_DOMAIN_BALL)
+    assert (W.BC_ZERO, W.BC_FACE_GRID, W.PREC_MIXED_KAHAN, W.PAIR_INDEPENDENT) == (
+        F.FK_BC_ZERO, F.FK_BC_FACE_GRID, F.FK_MIXED_KAHAN, F.FK_PAIR_INDEPENDENT)
+
+
 def test_struct_layouts_match_the_c_compiler(tmp_path):
     # every field offset and struct size of the binding against gcc's view of
     # the header
