@@ -290,6 +290,13 @@ fk_status fk_gz_adjoint(const double *stations, int64_t n_stations, const fk_box
 fk_status fk_stream_blocks(const uint32_t *counters, int64_t n_items, uint64_t seed, uint32_t *words,
                            double *normals_f64, float *normals_f32, void *hip_stream);
 
+/* Merges per-station results of two disjoint walk ranges of the same
+ * stations (e.g. path_offset ranges run separately, on one GPU or several):
+ * the sample mean of eq. 11 and the unbiased variance of the union (Chan's
+ * pairwise update), its standard error, and the summed step tallies.  a, b,
+ * out: HOST arrays of n fk_stat (out may alias a or b). */
+fk_status fk_merge_stats(const fk_stat *a, const fk_stat *b, int64_t n, fk_stat *out);
+
 /* Moving-average smoothing of a station profile (paper section 4.1): value k
  * is replaced by the mean of the values in the widest window of at most
  * `span` (odd) points centred on k that fits in the profile, so the window

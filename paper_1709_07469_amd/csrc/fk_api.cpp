@@ -888,6 +888,41 @@ fk_status fk_autotune(int32_t kind, const double* stations, int64_t n_stations, 
     return FK_OK;
 }
 
+fk_status fk_merge_stats(const fk_stat* a, const fk_stat* b, int64_t n, fk_stat* out)
+{
+    if (n < 0) return fail(FK_EINVAL, "n < 0");
+    if (n > 0 && (!a || !b || !out)) return fail(FK_EINVAL, "NULL statistics");
+    for (int64_t s = 0; s < n; ++s) {
+        const fk_stat x = a[s], y = b[s];
+        fk_stat r{};
+        r.n = x.n + y.n;
+        r.n_trunc = x.n_trunc + y.n_trunc;
+        r.sum_steps = x.sum_steps + y.sum_steps;
+        r.max_steps = x.max_steps > y.max_steps ? x.max_steps : y.max_steps;
+        const double walks = (double)(x.n + x.n_trunc + y.n + y.n_trunc);
+        r.mean_steps = walks > 0.0 ? (double)r.sum_steps / walks : 0.0;
+        if (r.n == 0) {
+            r.mean = r.var = r.se = std::nan("");
+        } else if (x.n == 0 || y.n == 0) {
+            const fk_stat& z = x.n ? x : y;
+            r.mean = z.mean;
+            r.var = z.var;
+            r.se = z.se;
+        } else {
+            const double na = (double)x.n, nb = (double)y.n, nn = (double)r.n;
+            const double d = y.mean - x.mean;
+            r.mean = x.mean + d * (nb / nn);
+            const double m2a = x.n > 1 ? x.var * (na - 1.0) : 0.0;
+            const double m2b = y.n > 1 ? y.var * (nb - 1.0) : 0.0;
+            const double m2 = m2a + m2b + d * d * (na * nb / nn);
+            r.var = r.n > 1 ? m2 / (nn - 1.0) : std::nan("");
+            r.se = r.n > 1 ? std::sqrt(r.var / nn) : std::nan("");
+        }
+        out[s] = r;
+    }
+    return FK_OK;
+}
+
 fk_status fk_moving_average(const double* values, const double* se, int64_t n, int32_t span, double* out_values,
                             double* out_se)
 {

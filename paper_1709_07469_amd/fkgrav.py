@@ -119,6 +119,8 @@ def lib():
             L.fk_stream_blocks.restype = i32
             L.fk_autotune.argtypes = [i32, p, i64, p, p, p, p, p, p, sz, p, p, p]
             L.fk_autotune.restype = i32
+            L.fk_merge_stats.argtypes = [p, p, i64, p]
+            L.fk_merge_stats.restype = i32
             L.fk_moving_average.argtypes = [p, p, i64, i32, p, p]
             L.fk_moving_average.restype = i32
             L.fk_set_launch.argtypes = [i32, p]
@@ -253,6 +255,18 @@ def fk_autotune(kind, stations, box, source, bc, params, out, workspace, stream=
                              C.byref(bc), C.byref(params), _ptr(out), _ptr(workspace), int(workspace.numel()),
                              _stream_handle(stream), C.byref(best), C.byref(ms)))
     return {"block": best.block, "blocks_per_cu": best.blocks_per_cu, "grab": best.grab}, ms.value
+
+
+def fk_merge_stats(a, b):
+    """Merges two structured arrays of station statistics (STAT_DTYPE) from
+    disjoint walk ranges of the same stations (host)."""
+    a = np.ascontiguousarray(a, dtype=STAT_DTYPE)
+    b = np.ascontiguousarray(b, dtype=STAT_DTYPE)
+    if a.shape != b.shape:
+        raise ValueError("statistics of different station counts")
+    out = np.empty_like(a)
+    _check(lib().fk_merge_stats(_ptr(a), _ptr(b), len(a), _ptr(out)))
+    return out
 
 
 def fk_moving_average(values, se=None, span: int = 5):
