@@ -72,13 +72,13 @@ __device__ __forceinline__ void merge(Acc& a, const Acc& b)
     a.n = n;
 }
 
-__device__ __forceinline__ double batch_sample(const BatchDesc& D, int64_t j, uint32_t steps)
+__device__ __forceinline__ double batch_sample(const BatchDesc& D, int64_t j, uint32_t steps, const DataTables& tb)
 {
     double v = __builtin_nan("");
     if ((steps & kCapFlag) == 0) {
         const ExitRecord r = D.c.exits[j];
         const double e[3] = {r.x, r.y, r.z};
-        v = boundary_value(D.bc, D.c.lo, D.c.hi, D.c.G, e) - D.c.w * r.S;
+        v = boundary_value(D.bc, D.c.lo, D.c.hi, D.c.G, e, tb) - D.c.w * r.S;
     }
     D.values[j] = v;
     return v;
@@ -97,6 +97,9 @@ __global__ void __launch_bounds__(kReduceBlock) batch_chunk_kernel(const BatchAr
     const int64_t i1 = (i0 + B.chunk < N) ? i0 + B.chunk : N;
     const double two_h = 2.0 * D.c.h;
 
+    DataTables tb{nullptr, nullptr};
+    if (D.bc.kind == FK_BC_PRISMS) tb = fill_data_tables();     // one problem per block: uniform
+
     Acc a{0.0, 0.0, 0.0, 0, 0, 0};
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kReduceBlock) {
         double v;
@@ -107,15 +110,15 @@ __global__ void __launch_bounds__(kReduceBlock) batch_chunk_kernel(const BatchAr
             const uint32_t sp = D.c.steps[j], sm = D.c.steps[j + 1];
             capped = ((sp | sm) & kCapFlag) != 0;
             st = (sp & ~kCapFlag) + (sm & ~kCapFlag);
-            const double up = batch_sample(D, j, sp);
-            const double um = batch_sample(D, j + 1, sm);
+            const double up = batch_sample(D, j, sp, tb);
+            const double um = batch_sample(D, j + 1, sm, tb);
             v = (up - um) / two_h;
         } else {
             const int64_t j = s * N + i;
             const uint32_t sp = D.c.steps[j];
             capped = (sp & kCapFlag) != 0;
             st = sp & ~kCapFlag;
-            v = batch_sample(D, j, sp);
+            v = batch_sample(D, j, sp, tb);
         }
         a.sum_steps += st;
         a.max_steps = (int64_t)st > a.max_steps ? (int64_t)st : a.max_steps;

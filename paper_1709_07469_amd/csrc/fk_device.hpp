@@ -406,9 +406,64 @@ __device__ __forceinline__ void intersect_ball(const double* c, double r2, const
 
 // ln(a + sqrt(a^2 + s)) with s = sum of the other two squares; for a < 0 the
 // sum a + r cancels, and a + r = s / (r - a) is used instead.
-__device__ __forceinline__ double log_shift(double a, double r, double s)
+// Tables of the prism closed form, in LDS: the log grid of BmTables and
+// atan(k/64), k = 0..64 (library atan, filled at the start of the launch).
+struct AtanTable {
+    static constexpr int kN = 64;
+    double at[kN + 1];
+};
+
+struct DataTables {
+    const BmTables* bm;
+    const AtanTable* at;
+};
+
+__device__ __forceinline__ AtanTable* atan_table()
 {
-    return a >= 0.0 ? log(a + r) : log(s) - log(r - a);
+    __shared__ AtanTable t;
+    return &t;
+}
+
+// Fills both tables with every thread of the block; ends with a barrier.
+__device__ __forceinline__ DataTables fill_data_tables()
+{
+    BmTables* bm = bm_tables();
+    AtanTable* at = atan_table();
+    for (int i = threadIdx.x; i <= AtanTable::kN; i += blockDim.x) at->at[i] = atan((double)i / AtanTable::kN);
+    fill_bm_tables(*bm);
+    return DataTables{bm, at};
+}
+
+// ln x for a positive finite x, from the table-driven -2 ln x.
+__device__ __forceinline__ double ln_t(double x, const BmTables& T) { return -0.5 * neg2_log_t(x, T); }
+
+// atan(n / d) for finite n and d != 0: t = min(|n|, |d|) / max(|n|, |d|) in
+// [0, 1] (one division), c = k/64 the nearest grid point and
+// atan t = atan c + atan(delta), delta = (t - c)/(1 + t c), |delta| <= 1/128,
+// by its series to delta^9 (truncation below 1e-24); pi/2 - atan t when
+// |n| > |d|, and the sign of n/d.
+__device__ __forceinline__ double atan_q(double n, double d, const AtanTable& A)
+{
+    const double an = fabs(n), ad = fabs(d);
+    const bool swap = an > ad;
+    const double t = swap ? ad / an : an / ad;
+    const double k = __builtin_rint(t * (double)AtanTable::kN);
+    const double c = k * (1.0 / AtanTable::kN);
+    const double dl = (t - c) / fma(t, c, 1.0);
+    const double z = dl * dl;
+    double p = fma(z, 0x1.c71c71c71c71cp-4, -0x1.2492492492492p-3);   // 1/9, -1/7
+    p = fma(p, z, 0x1.999999999999ap-3);                                // 1/5
+    p = fma(p, z, -0x1.5555555555555p-2);                               // -1/3
+    double a = A.at[(int)k] + fma(dl * z, p, dl);
+    if (swap) a = 0x1.921fb54442d18p+0 - a;                             // pi/2
+    return ((n < 0.0) != (d < 0.0)) ? -a : a;
+}
+
+// ln(a + r) with r = sqrt(a^2 + s), s > 0: for a < 0 the sum cancels, and
+// a + r = s / (r - a) is used instead.
+__device__ __forceinline__ double log_shift(double a, double r, double s, const BmTables& T)
+{
+    return ln_t(a >= 0.0 ? a + r : s / (r - a), T);
 }
 
 // Newtonian integral of the unit-density prism [lo, hi] seen from p: the
@@ -417,8 +472,10 @@ __device__ __forceinline__ double log_shift(double a, double r, double s)
 //   - X^2/2 atan(YZ/(Xr)) - Y^2/2 atan(ZX/(Yr)) - Z^2/2 atan(XY/(Zr))
 // with corner (X, Y, Z) = corner - p and sign + at the upper corner (Nagy,
 // Papp & Benedek 2000); a term whose prefactor is zero vanishes.
-__device__ inline double prism_newton(const double* q, double px, double py, double pz)
+__device__ inline double prism_newton(const double* q, double px, double py, double pz, const DataTables& tb)
 {
+    const BmTables& T = *tb.bm;
+    const AtanTable& A = *tb.at;
     double v = 0.0;
     for (int corner = 0; corner < 8; ++corner) {
         const double X = ((corner & 1) ? q[3] : q[0]) - px;
@@ -427,12 +484,12 @@ __device__ inline double prism_newton(const double* q, double px, double py, dou
         const double X2 = X * X, Y2 = Y * Y, Z2 = Z * Z;
         const double r = sqrt(X2 + Y2 + Z2);
         double f = 0.0;
-        if (X * Y != 0.0) f += X * Y * log_shift(Z, r, X2 + Y2);
-        if (Y * Z != 0.0) f += Y * Z * log_shift(X, r, Y2 + Z2);
-        if (Z * X != 0.0) f += Z * X * log_shift(Y, r, Z2 + X2);
-        if (X != 0.0) f -= 0.5 * X2 * atan(Y * Z / (X * r));
-        if (Y != 0.0) f -= 0.5 * Y2 * atan(Z * X / (Y * r));
-        if (Z != 0.0) f -= 0.5 * Z2 * atan(X * Y / (Z * r));
+        if (X * Y != 0.0) f += X * Y * log_shift(Z, r, X2 + Y2, T);
+        if (Y * Z != 0.0) f += Y * Z * log_shift(X, r, Y2 + Z2, T);
+        if (Z * X != 0.0) f += Z * X * log_shift(Y, r, Z2 + X2, T);
+        if (X != 0.0) f -= 0.5 * X2 * atan_q(Y * Z, X * r, A);
+        if (Y != 0.0) f -= 0.5 * Y2 * atan_q(Z * X, Y * r, A);
+        if (Z != 0.0) f -= 0.5 * Z2 * atan_q(X * Y, Z * r, A);
         // sign (-1)^(i+j+k) with index 1 = lower, 2 = upper corner: positive
         // when the number of upper coordinates is odd
         const int uppers = (corner & 1) + ((corner >> 1) & 1) + ((corner >> 2) & 1);
@@ -471,7 +528,7 @@ __device__ inline double face_grid(const BoundaryArgs& bc, const double* lo, con
 }
 
 __device__ inline double boundary_value(const BoundaryArgs& bc, const double* lo, const double* hi, double G,
-                                        const double e[3])
+                                        const double e[3], const DataTables& tb)
 {
     const double x = e[0], y = e[1], z = e[2];
     switch (bc.kind) {
@@ -493,7 +550,7 @@ __device__ inline double boundary_value(const BoundaryArgs& bc, const double* lo
         double v = 0.0;
         for (int j = 0; j < bc.n_items; ++j) {
             const double* q = bc.items[j];
-            v += -G * q[6] * prism_newton(q, x, y, z);
+            v += -G * q[6] * prism_newton(q, x, y, z, tb);
         }
         return v;
     }

@@ -58,13 +58,13 @@ __device__ __forceinline__ Acc shfl_down_acc(const Acc& a, int off)
 }
 
 // The sample of walk j, stored for inspection: NaN for a capped walk.
-__device__ __forceinline__ double sample(const ReduceArgs& R, int64_t j, uint32_t steps)
+__device__ __forceinline__ double sample(const ReduceArgs& R, int64_t j, uint32_t steps, const DataTables& tb)
 {
     double v = __builtin_nan("");
     if ((steps & kCapFlag) == 0) {
         const ExitRecord r = R.exits[j];
         const double e[3] = {r.x, r.y, r.z};
-        v = boundary_value(R.bc, R.lo, R.hi, R.G, e) - R.w * r.S;
+        v = boundary_value(R.bc, R.lo, R.hi, R.G, e, tb) - R.w * r.S;
     }
     R.values[j] = v;
     return v;
@@ -78,6 +78,9 @@ __global__ void __launch_bounds__(kReduceBlock) chunk_kernel(const ReduceArgs R)
     const int64_t i0 = c * R.chunk;
     const int64_t i1 = (i0 + R.chunk < R.N) ? i0 + R.chunk : R.N;
 
+    DataTables tb{nullptr, nullptr};
+    if (R.bc.kind == FK_BC_PRISMS) tb = fill_data_tables();     // uniform: every thread takes it
+
     Acc a{0.0, 0.0, 0.0, 0, 0, 0};
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kReduceBlock) {
         double v;
@@ -88,15 +91,15 @@ __global__ void __launch_bounds__(kReduceBlock) chunk_kernel(const ReduceArgs R)
             const uint32_t sp = R.steps[j], sm = R.steps[j + 1];
             capped = ((sp | sm) & kCapFlag) != 0;
             st = (sp & ~kCapFlag) + (sm & ~kCapFlag);
-            const double up = sample(R, j, sp);
-            const double um = sample(R, j + 1, sm);
+            const double up = sample(R, j, sp, tb);
+            const double um = sample(R, j + 1, sm, tb);
             v = (up - um) / R.two_h;
         } else {
             const int64_t j = s * R.N + i;
             const uint32_t sp = R.steps[j];
             capped = (sp & kCapFlag) != 0;
             st = sp & ~kCapFlag;
-            v = sample(R, j, sp);
+            v = sample(R, j, sp, tb);
         }
         a.sum_steps += st;
         a.max_steps = (int64_t)st > a.max_steps ? (int64_t)st : a.max_steps;
