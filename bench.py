@@ -136,17 +136,22 @@ def cpu_baseline(prob, seconds):
 
 
 # The paper's Table 1: seconds on one Tesla K20Xm for experiment 1 (31
-# stations, potential) at its time steps Delta t and walk counts N.  Lengths
-# are read as km (the only unit that makes these times consistent with the
-# expected exit time of the 10 km ball).
-PAPER_TABLE1_N = (1024, 2048, 4096, 5120, 10240, 20480, 40960, 51200)
-PAPER_TABLE1_S = {
-    0.1: (0.3, 0.4, 0.4, 0.4, 0.5, 0.5, 0.9, 1.1),
-    0.05: (0.8, 0.9, 1.0, 1.0, 1.1, 1.2, 2.0, 2.5),
-    0.01: (4.8, 5.3, 5.8, 5.9, 6.4, 7.1, 11.5, 14.3),
-    0.005: (9.9, 10.9, 12.2, 12.3, 13.0, 14.7, 24.1, 29.4),
-    0.001: (52.8, 55.6, 59.6, 61.1, 65.7, 75.8, 125.6, 155.7),
-}
+# stations, potential) at its time steps Delta t and walk counts N, read from
+# tests/golden/paper_experiments.txt.  Lengths are read as km (the only unit
+# that makes these times consistent with the expected exit time of the 10 km
+# ball).
+def paper_table1_reference():
+    n, rows = None, {}
+    with open(os.path.join(ROOT, "tests", "golden", "paper_experiments.txt")) as f:
+        for line in f:
+            w = line.split()
+            if not w or w[0].startswith("#"):
+                continue
+            if w[0] == "table1_N":
+                n = tuple(int(v) for v in w[1:])
+            elif w[0] == "table1":
+                rows[float(w[1])] = tuple(float(v) for v in w[2:])
+    return n, rows
 
 
 def paper_table1(precision_name):
@@ -160,10 +165,11 @@ def paper_table1(precision_name):
     from paper_1709_07469_amd import workloads as W
 
     prec = W.PREC_F64 if precision_name == "f64" else W.PREC_MIXED_F64ACC
+    table_n, table_s = paper_table1_reference()
     rows, ours_total, paper_total, steps_total = [], 0.0, 0.0, 0
-    for dtp, paper_s in PAPER_TABLE1_S.items():
+    for dtp, paper_s in table_s.items():
         row = []
-        for N, ps in zip(PAPER_TABLE1_N, paper_s):
+        for N, ps in zip(table_n, paper_s):
             prob = W.paper_ball(dt_paper=dtp, paths_per_station=N, precision=prec)
             P = F.Prepared(prob)
             ws = F.alloc_workspace(F.fk_workspace_bytes(0, prob.n_stations, P.params))
@@ -186,7 +192,7 @@ def paper_table1(precision_name):
         rows.append({"dt_paper": dtp, "seconds": row, "paper_k20xm_seconds": list(paper_s)})
     return {"workload": "paper experiment 1: ball R = 10 km (lengths in km), zero data, cube [0,100 m]^3 of "
                         "2000 kg/m^3, 31 stations y = 50 m, z = 200 m, x = -100..200 m; potential",
-            "precision": precision_name, "N": list(PAPER_TABLE1_N), "rows": rows,
+            "precision": precision_name, "N": list(table_n), "rows": rows,
             "total_seconds": ours_total, "paper_total_seconds": paper_total,
             "speedup_vs_paper_total": paper_total / ours_total, "steps": steps_total,
             "steps_per_s": steps_total / ours_total}
@@ -313,6 +319,8 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="bat
         mu, mg = mstats()
         msteps = int(mu["sum_steps"].sum()) + int(mg["sum_steps"].sum())
         mval = msteps * K / mel
+        bstep, _ = make_stepper(pmix, "batched")
+        bel, _ = timed(bstep, K, 1)
         # the two kernels draw different normals (FP32 and FP64 streams), so
         # their estimates are independent: differences are scaled by the
         # standard error of the difference, sqrt(se_a^2 + se_b^2)
@@ -320,6 +328,7 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="bat
         dg = float(np.max(np.abs(mg["mean"] - sg["mean"]) / np.hypot(mg["se"], sg["se"])))
         result["mixed"] = {"value": mval, "unit": "Brownian steps/s", "launch": "separate",
                            "speedup_vs_f64": mval / value,
+                           "batched_value": msteps * K / bel,
                            "max_abs_diff_vs_f64_in_combined_se": {"u": du, "g_z": dg}}
 
     if want_paper:
