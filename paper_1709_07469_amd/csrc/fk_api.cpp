@@ -368,7 +368,8 @@ void fill_source_f32(fk::SourceF32& S, const fk_source* s)
 // The general stepping loop (ball domain, bridge test) or the box loop.
 bool general_loop(const fk_params* p) { return p->domain == FK_DOMAIN_BALL || p->exit_rule == FK_EXIT_BRIDGE; }
 
-fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false, bool gen = false)
+fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false, bool gen = false,
+                      bool shared = false)
 {
     fk_launch l;
     {
@@ -381,7 +382,7 @@ fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool b
     if (cus <= 0) return fail(FK_EDEVICE, "could not query the compute-unit count");
     int bpc = l.blocks_per_cu;
     if (bpc <= 0) {
-        const hipError_t oe = batch ? fk::batch_occupancy(precision, l.block, &bpc, gen)
+        const hipError_t oe = batch ? fk::batch_occupancy(precision, l.block, &bpc, gen, shared)
                                     : fk::walk_occupancy(precision, l.block, &bpc, gen);
         if (oe != hipSuccess || bpc <= 0)
             return fail(FK_EDEVICE, "occupancy query failed for block %d", l.block);
@@ -544,7 +545,27 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
     fk::LaunchCfg cfg;
     bool gen = false;
     for (int32_t m = 0; m < n; ++m) gen = gen || general_loop(&probs[m].params);
-    if ((st = plan_launch(precision, BL.n_tasks, &cfg, true, gen)) != FK_OK) return st;
+    // one source for the whole batch (e.g. u and g_z of one model): the walk
+    // kernel then reads it from its arguments instead of per-lane descriptors
+    fk::BatchArgs A;
+    std::memset(&A, 0, sizeof A);
+    bool shared = true;
+    if (precision == FK_F64) {
+        fill_source_f64(A.src64, &probs[0].source);
+        for (int32_t m = 1; m < n && shared; ++m) {
+            fk::SourceF64 o;
+            fill_source_f64(o, &probs[m].source);
+            shared = std::memcmp(&o, &A.src64, sizeof o) == 0;
+        }
+    } else {
+        fill_source_f32(A.src32, &probs[0].source);
+        for (int32_t m = 1; m < n && shared; ++m) {
+            fk::SourceF32 o;
+            fill_source_f32(o, &probs[m].source);
+            shared = std::memcmp(&o, &A.src32, sizeof o) == 0;
+        }
+    }
+    if ((st = plan_launch(precision, BL.n_tasks, &cfg, true, gen, shared)) != FK_OK) return st;
 
     std::vector<int64_t> task_off(n + 1, 0), block_off(n + 1, 0);
     int64_t station_base = 0;
@@ -583,8 +604,6 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
                                    reinterpret_cast<const uint64_t*>(block_off.data()), n + 1, stream);
     if (e != hipSuccess) return fail(FK_EDEVICE, "offset upload failed: %s", hipGetErrorString(e));
 
-    fk::BatchArgs A;
-    std::memset(&A, 0, sizeof A);
     A.desc = descs;
     A.task_off = reinterpret_cast<const int64_t*>(ws + BL.task_off);
     A.block_off = reinterpret_cast<const int64_t*>(ws + BL.block_off);
@@ -598,7 +617,7 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
 
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     const bool timed = timing_begin(&ev, stream);
-    e = fk::launch_batch_walk(A, cfg, stream, gen);
+    e = fk::launch_batch_walk(A, cfg, stream, gen, shared);
     if (timed) timing_end(ev, stream);
     if (e != hipSuccess) return fail(FK_EDEVICE, "batch walk launch failed: %s", hipGetErrorString(e));
     e = fk::launch_batch_reduce(A, BL.n_blocks, BL.n_stations, stream);

@@ -168,6 +168,11 @@ struct BatchArgs {
     uint32_t total_waves;
     int32_t precision;
     int64_t chunk;
+    // when every problem of the batch has the same source, that source (the
+    // walk kernel then reads it from the kernel arguments, as a single
+    // problem's launch does)
+    SourceF64 src64;
+    SourceF32 src32;
 };
 
 struct LaunchCfg {
@@ -196,8 +201,8 @@ hipError_t launch_stream_blocks(const uint32_t* ctr, int64_t n, uint32_t key0, u
 // captured graph replays it), the persistent walk kernel over all problems,
 // and the batched reduction.
 hipError_t launch_write_words(uint64_t* dst, const uint64_t* host_words, int64_t n_words, hipStream_t stream);
-hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, bool gen);
+hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, bool gen, bool shared);
 hipError_t launch_batch_reduce(const BatchArgs& a, int64_t n_blocks, int64_t n_station_threads, hipStream_t stream);
-hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, bool gen = false);
+hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, bool gen = false, bool shared = false);
 
 }  // namespace fk

@@ -257,6 +257,17 @@ struct SourceOf<false> {
     __device__ static const SourceF32& get(const BatchDesc& D) { return D.s32; }
 };
 
+// The batch's shared source, in the kernel arguments.
+template <bool F64>
+__device__ __forceinline__ const typename std::conditional<F64, SourceF64, SourceF32>::type& shared_source(
+    const BatchArgs& A)
+{
+    if constexpr (F64)
+        return A.src64;
+    else
+        return A.src32;
+}
+
 // Stepping parameters of the problem a lane is walking.  In single-problem
 // launches they are the same for every lane (held in scalar registers); in a
 // batch each lane loads its problem's at the start of a walk.
@@ -364,15 +375,15 @@ struct Walker {
     // the walk ends here, with how = 0: it left the domain (a = last inside
     // point, e = the first point outside); how = 1: it reached max_steps;
     // how = 2 + f: the bridge test stopped it at face f (e = the step's end).
-    __device__ __forceinline__ bool step(const LaneProblem<F64>& P, T z0, T z1, T z2, T& a0, T& a1, T& a2, T& e0,
-                                         T& e1, T& e2, int& how)
+    __device__ __forceinline__ bool step(const LaneProblem<F64>& P, const typename Prec<F64>::Src& src, T z0, T z1,
+                                         T z2, T& a0, T& a1, T& a2, T& e0, T& e1, T& e2, int& how)
     {
         const T y0 = Prec<F64>::fmat(P.sdt, z0, x0);
         const T y1 = Prec<F64>::fmat(P.sdt, z1, x1);
         const T y2 = Prec<F64>::fmat(P.sdt, z2, x2);
         T rn = T(0);
         if (!ADJ) {
-            rn = Prec<F64>::rho(*P.src, y0, y1, y2);
+            rn = Prec<F64>::rho(src, y0, y1, y2);
             if (F64) {
                 S = S + (double)(rp + rn);
             } else if (KAHAN) {
@@ -399,7 +410,7 @@ struct Walker {
             if (!(deep && deep_y)) stop = bridge_stop(P, n - 1, y0, y1, y2);
             deep = deep_y;
         }
-        if (ADJ) sc.add(Prec<F64>::voxel(*P.src, y0, y1, y2), (out || stop >= 0) ? 1 : 2);
+        if (ADJ) sc.add(Prec<F64>::voxel(src, y0, y1, y2), (out || stop >= 0) ? 1 : 2);
         if (out || stop >= 0) {
             a0 = x0; a1 = x1; a2 = x2;
             e0 = y0; e1 = y1; e2 = y2;
@@ -463,7 +474,7 @@ struct Walker {
 // ---------------------------------------------------------------------------
 // The kernel body.
 // ---------------------------------------------------------------------------
-template <bool F64, bool KAHAN, bool ADJ, bool BATCH, bool GEN, class Args>
+template <bool F64, bool KAHAN, bool ADJ, bool BATCH, bool GEN, bool SHARED, class Args>
 __device__ __forceinline__ void walk_body(const Args& A)
 {
     using T = typename Prec<F64>::T;
@@ -494,6 +505,13 @@ __device__ __forceinline__ void walk_body(const Args& A)
         Q = Queue{A.c.queue, (uint64_t)A.c.n_tasks, (uint32_t)A.c.grab, A.c.total_waves};
         P.load(A.c, A.src);
     }
+    // the density source of the lane's walk: the launch's (kernel arguments),
+    // the batch's shared one (kernel arguments), or the lane's problem's
+    auto source = [&]() -> const typename Prec<F64>::Src& {
+        if constexpr (!BATCH) return A.src;
+        else if constexpr (SHARED) return shared_source<F64>(A);
+        else return *P.src;
+    };
     Pool pool{0ull, 0ull, Q.n_tasks, false};
     Walker<F64, KAHAN, ADJ, GEN> W;
     W.active = false;
@@ -516,7 +534,10 @@ __device__ __forceinline__ void walk_body(const Args& A)
                 const int m = find_problem(A.task_off, A.n_problems, (int64_t)got);
                 const BatchDesc& D = A.desc[m];
                 t = got - (uint64_t)A.task_off[m];
-                P.load(D.c, SourceOf<F64>::get(D));
+                if constexpr (SHARED)
+                    P.load(D.c, shared_source<F64>(A));
+                else
+                    P.load(D.c, SourceOf<F64>::get(D));
                 Cp = &D.c;
             } else {
                 Cp = &A.c;
@@ -547,9 +568,9 @@ __device__ __forceinline__ void walk_body(const Args& A)
                     W.sc.v = -1;
                     W.sc.c = 0;
                     W.sc.sign = ti.w ? -1 : 1;
-                    W.sc.add(Prec<F64>::voxel(*P.src, W.x0, W.x1, W.x2), 1);
+                    W.sc.add(Prec<F64>::voxel(source(), W.x0, W.x1, W.x2), 1);
                 } else {
-                    W.rp = Prec<F64>::rho(*P.src, W.x0, W.x1, W.x2);
+                    W.rp = Prec<F64>::rho(source(), W.x0, W.x1, W.x2);
                 }
                 W.deep = false;
                 if (GEN && P.bridge) {
@@ -617,7 +638,8 @@ __device__ __forceinline__ void walk_body(const Args& A)
 #pragma unroll
                     for (int s = 0; s < MACRO; ++s) {
                         if (!done)
-                            done = W.step(P, zz[3 * s], zz[3 * s + 1], zz[3 * s + 2], a0, a1, a2, e0, e1, e2, how);
+                            done = W.step(P, source(), zz[3 * s], zz[3 * s + 1], zz[3 * s + 2], a0, a1, a2, e0, e1, e2,
+                                          how);
                     }
                 }
                 W.k += (uint32_t)B;
@@ -642,7 +664,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
         T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
 #pragma unroll
         for (int s = 0; s < MACRO; ++s) {
-            if (!done) done = W.step(P, z[3 * s], z[3 * s + 1], z[3 * s + 2], a0, a1, a2, e0, e1, e2, how);
+            if (!done) done = W.step(P, source(), z[3 * s], z[3 * s + 1], z[3 * s + 2], a0, a1, a2, e0, e1, e2, how);
         }
         if (done) W.finish(P, a0, a1, a2, e0, e1, e2, how);
     }
@@ -672,14 +694,14 @@ template <bool F64, bool KAHAN, bool ADJ, bool GEN>
 __global__ void __launch_bounds__(256, F64 ? FK_F64_BLOCKS_PER_CU : FK_F32_BLOCKS_PER_CU)
     walk_kernel(const typename std::conditional<F64, WalkArgsF64, WalkArgsF32>::type A)
 {
-    walk_body<F64, KAHAN, ADJ, false, GEN>(A);
+    walk_body<F64, KAHAN, ADJ, false, GEN, false>(A);
 }
 
-template <bool F64, bool KAHAN, bool GEN>
+template <bool F64, bool KAHAN, bool GEN, bool SHARED>
 __global__ void __launch_bounds__(256, GEN ? 1 : F64 ? FK_BATCH_F64_BLOCKS_PER_CU : FK_BATCH_F32_BLOCKS_PER_CU)
     batch_walk_kernel(const BatchArgs A)
 {
-    walk_body<F64, KAHAN, false, true, GEN>(A);
+    walk_body<F64, KAHAN, false, true, GEN, SHARED>(A);
 }
 
 }  // namespace
@@ -711,23 +733,26 @@ const void* walk_fn(int precision)
                                        : (const void*)walk_kernel<false, false, false, GEN>;
 }
 
-template <bool GEN>
+template <bool GEN, bool SHARED>
 const void* batch_fn(int precision)
 {
-    return precision == FK_F64 ? (const void*)batch_walk_kernel<true, false, GEN>
-         : precision == FK_MIXED_KAHAN ? (const void*)batch_walk_kernel<false, true, GEN>
-                                       : (const void*)batch_walk_kernel<false, false, GEN>;
+    return precision == FK_F64 ? (const void*)batch_walk_kernel<true, false, GEN, SHARED>
+         : precision == FK_MIXED_KAHAN ? (const void*)batch_walk_kernel<false, true, GEN, SHARED>
+                                       : (const void*)batch_walk_kernel<false, false, GEN, SHARED>;
 }
 
-template <bool GEN>
+template <bool GEN, bool SHARED>
 void launch_batch(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream)
 {
     if (a.precision == FK_F64)
-        hipLaunchKernelGGL((batch_walk_kernel<true, false, GEN>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+        hipLaunchKernelGGL((batch_walk_kernel<true, false, GEN, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0, stream,
+                           a);
     else if (a.precision == FK_MIXED_KAHAN)
-        hipLaunchKernelGGL((batch_walk_kernel<false, true, GEN>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+        hipLaunchKernelGGL((batch_walk_kernel<false, true, GEN, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0,
+                           stream, a);
     else
-        hipLaunchKernelGGL((batch_walk_kernel<false, false, GEN>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+        hipLaunchKernelGGL((batch_walk_kernel<false, false, GEN, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0,
+                           stream, a);
 }
 
 }  // namespace
@@ -763,18 +788,19 @@ hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, bool gen
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
-hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, bool gen)
+hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, bool gen, bool shared)
 {
     if (gen)
-        launch_batch<true>(a, cfg, stream);
+        shared ? launch_batch<true, true>(a, cfg, stream) : launch_batch<true, false>(a, cfg, stream);
     else
-        launch_batch<false>(a, cfg, stream);
+        shared ? launch_batch<false, true>(a, cfg, stream) : launch_batch<false, false>(a, cfg, stream);
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, bool gen)
+hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, bool gen, bool shared)
 {
-    const void* fn = gen ? batch_fn<true>(precision) : batch_fn<false>(precision);
+    const void* fn = gen ? (shared ? batch_fn<true, true>(precision) : batch_fn<true, false>(precision))
+                         : (shared ? batch_fn<false, true>(precision) : batch_fn<false, false>(precision));
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
