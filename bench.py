@@ -15,12 +15,13 @@ in-kernel step counts over the event-timed region), the ALU roofline of the
 walk kernel, station estimates per second at fixed relative standard error,
 the mixed-precision kernel on the same workload, the paper's Table 1
 workload (its experiment 1 at every time step and walk count, next to the
-K20Xm times it reports), and the CPU oracle timed on a bounded sample on the
-host.
+K20Xm times it reports), the 32-model batched workload in one graph-captured
+launch (default and autotuned launch settings), and the CPU oracle timed on
+a bounded sample on the host.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64|mixed]
                   [--launch batched|separate] [--no-cpu-baseline] [--cpu-seconds S]
-                  [--no-paper-table]
+                  [--no-paper-table] [--no-batched-models]
 """
 from __future__ import annotations
 
@@ -258,7 +259,61 @@ def timed(step, K, Wm, walk_timing=False):
     return e0.elapsed_time(e1) / 1e3, walk_ms
 
 
-def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="batched"):
+def batched_models():
+    """The uneven batched workload: 32 random 64^3 voxel models (1-8 prisms
+    each, 8-256 stations, 1e4-1e6 walks per station), mixed precision, in one
+    persistent launch captured in a HIP graph; timed with the default launch
+    setting and with the one the autotuner picks on the same batch at 5 % of
+    its walks."""
+    import torch
+
+    from paper_1709_07469_amd import autotune
+    from paper_1709_07469_amd import fkgrav as F
+    from paper_1709_07469_amd import workloads as W
+
+    probs = W.cfg4()
+    kinds = [0] * len(probs)
+    PB = F.PreparedBatch(probs, kinds)
+    ws = F.alloc_workspace(F.fk_batch_workspace_bytes(PB.problems))
+    out = F.alloc_stats(PB.n_out)
+
+    def graph_seconds():
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            F.fk_solve_batch(PB.problems, out, ws)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            F.fk_solve_batch(PB.problems, out, ws)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    keep = F.fk_get_launch(W.PREC_MIXED_F64ACC)
+    t_default = graph_seconds()
+    steps = int(F.stats_to_numpy(out)[:PB.n_out]["sum_steps"].sum())
+    tuned = autotune.tune_batch(probs, kinds, walk_fraction=0.05)
+    t_tuned = graph_seconds()
+    F.fk_set_launch(W.PREC_MIXED_F64ACC, keep["block"], keep["blocks_per_cu"], keep["grab"])
+    del ws
+    torch.cuda.empty_cache()
+    return {"workload": "32 voxel models (64^3 FP32 grids, 1-8 prisms), 8-256 stations, 1e4-1e6 walks/station, "
+                        "mixed precision, one graph-captured persistent launch",
+            "models": len(probs), "stations": PB.n_out,
+            "walks": int(sum(p.n_stations * p.paths_per_station for p in probs)), "steps": steps,
+            "default": {"seconds": t_default, "steps_per_s": steps / t_default, "launch": keep},
+            "tuned": {"seconds": t_tuned, "steps_per_s": steps / t_tuned,
+                      "launch": {k: tuned[k] for k in ("block", "blocks_per_cu", "grab")}}}
+
+
+def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="batched", want_models=True):
     import numpy as np
 
     from paper_1709_07469_amd import workloads as W
@@ -333,6 +388,8 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="bat
 
     if want_paper:
         result["paper_table1"] = paper_table1(precision_name)
+    if want_models and precision_name == "f64":
+        result["batched_models"] = batched_models()
     if want_cpu:
         result["cpu_baseline"] = cpu_baseline(prob, cpu_seconds)
     return result
@@ -348,6 +405,7 @@ def main():
                     help="u and g_z in one persistent launch (default) or in two")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-table", action="store_true", help="skip the paper's Table 1 workload")
+    ap.add_argument("--no-batched-models", action="store_true", help="skip the 32-model batched workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this many bytes (calibrates HBM byte counters)")
@@ -362,7 +420,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     res = run(a.precision, max(1, a.steps), max(0, a.warmup), a.cpu_seconds, not a.no_cpu_baseline,
-              not a.no_paper_table, a.launch)
+              not a.no_paper_table, a.launch, not a.no_batched_models)
     if a.copy_bytes > 0:
         src = torch.ones(a.copy_bytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

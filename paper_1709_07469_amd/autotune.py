@@ -6,7 +6,9 @@ the problem, installs the fastest setting for the problem's precision and
 records it in a JSON cache keyed by device name, precision, kind and the
 workload's shape (stations, walks per station, source kind, steps per walk
 order of magnitude).  ``apply_cached(problem, kind)`` installs a cached
-setting without timing anything.  The cache file is FKGRAV_TUNE_CACHE, or
+setting without timing anything.  ``tune_batch(problems, kinds)`` times the
+same candidates on a scaled-down copy of a whole batch (every problem with a
+fraction of its walks), so the choice reflects the batch's mix of problems.  The cache file is FKGRAV_TUNE_CACHE, or
 ~/.cache/fkgrav_tune.json.  Settings never change results, only time.
 """
 from __future__ import annotations
@@ -72,3 +74,37 @@ def apply_cached(prob, kind: int = 0) -> dict | None:
     if s:
         F.fk_set_launch(prob.precision, s["block"], s["blocks_per_cu"], s["grab"])
     return s
+
+
+BATCH_CANDIDATES = [(b, r, g) for b in (64, 128, 256) for r in (0, 2) for g in (16, 32, 64)]
+
+
+def tune_batch(probs, kinds, walk_fraction: float = 0.05, min_walks: int = 64) -> dict:
+    """Times every candidate launch setting (block size, resident blocks per
+    CU -- 0 for the occupancy limit --, queue-run length) on the batch with
+    each problem's walks cut to walk_fraction, installs the fastest for the
+    batch's precision and returns it with its time.  Results never depend on
+    the setting."""
+    import torch
+    small = [p.replace(paths_per_station=max(min_walks, int(p.paths_per_station * walk_fraction))) for p in probs]
+    PB = F.PreparedBatch(small, kinds)
+    ws = F.alloc_workspace(F.fk_batch_workspace_bytes(PB.problems))
+    out = F.alloc_stats(PB.n_out)
+    prec = probs[0].precision
+    best = None
+    for block, bpc, grab in BATCH_CANDIDATES:
+        F.fk_set_launch(prec, block, bpc, grab)
+        F.fk_solve_batch(PB.problems, out, ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        F.fk_solve_batch(PB.problems, out, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        if best is None or ms < best["tune_ms"]:
+            best = {"block": block, "blocks_per_cu": bpc, "grab": grab, "tune_ms": ms}
+    F.fk_set_launch(prec, best["block"], best["blocks_per_cu"], best["grab"])
+    best["walk_fraction"] = walk_fraction
+    del ws
+    return best

@@ -62,3 +62,24 @@ def test_autotuner_installs_and_caches_a_setting(tmp_path, monkeypatch):
         assert again is not None and F.fk_get_launch(W.PREC_MIXED_F64ACC)["block"] == best["block"]
     finally:
         F.fk_set_launch(W.PREC_MIXED_F64ACC, keep["block"], keep["blocks_per_cu"], keep["grab"])
+
+
+def test_batch_autotuner_picks_a_candidate_and_keeps_results():
+    from paper_1709_07469_amd import autotune
+    from paper_1709_07469_amd import fkgrav as F
+    prec = W.PREC_MIXED_F64ACC
+    keep = F.fk_get_launch(prec)
+    probs = [m.replace(paths_per_station=400) for m in W.cfg4(n_models=3, precision=prec, n=32)]
+    kinds = [0, 1, 0]
+    try:
+        before, _, _, _ = F.solve_batch(probs, kinds)
+        best = autotune.tune_batch(probs, kinds, walk_fraction=0.25)
+        say("  batch tuning picked", best)
+        assert (best["block"], best["blocks_per_cu"], best["grab"]) in autotune.BATCH_CANDIDATES
+        got = F.fk_get_launch(prec)
+        assert (got["block"], got["blocks_per_cu"], got["grab"]) == (best["block"], best["blocks_per_cu"], best["grab"])
+        after, _, _, _ = F.solve_batch(probs, kinds)
+        for a, b in zip(before, after):
+            assert a.tobytes() == b.tobytes()
+    finally:
+        F.fk_set_launch(prec, keep["block"], keep["blocks_per_cu"], keep["grab"])
