@@ -132,7 +132,14 @@ def cpu_baseline(prob, seconds):
         if elapsed >= 0.6 * seconds or n >= prob.paths_per_station:
             break
         n = min(prob.paths_per_station, max(n + 1, int(n * min(8.0, 1.1 * seconds / max(elapsed, 1e-3)))))
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {"value": steps / elapsed, "unit": "Brownian steps/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "cpu": cpu,
             "sample": f"all {S} stations x first {n} walks, u and g_z (FP64): {steps} steps in {elapsed:.1f} s"}
 
 

@@ -3,6 +3,7 @@
 // and reduction kernels on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -365,10 +366,13 @@ void fill_source_f32(fk::SourceF32& S, const fk_source* s)
         for (int c = 0; c < 5; ++c) S.spheres[j][c] = (float)s->spheres[5 * j + c];
 }
 
-// The general stepping loop (ball domain, bridge test) or the box loop.
-bool general_loop(const fk_params* p) { return p->domain == FK_DOMAIN_BALL || p->exit_rule == FK_EXIT_BRIDGE; }
+// The stepping loop a problem needs: 0 box, 1 ball exit test, 2 bridge test.
+int loop_kind(const fk_params* p)
+{
+    return p->exit_rule == FK_EXIT_BRIDGE ? 2 : p->domain == FK_DOMAIN_BALL ? 1 : 0;
+}
 
-fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false, bool gen = false,
+fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false, int loop = 0,
                       bool shared = false)
 {
     fk_launch l;
@@ -382,8 +386,8 @@ fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool b
     if (cus <= 0) return fail(FK_EDEVICE, "could not query the compute-unit count");
     int bpc = l.blocks_per_cu;
     if (bpc <= 0) {
-        const hipError_t oe = batch ? fk::batch_occupancy(precision, l.block, &bpc, gen, shared)
-                                    : fk::walk_occupancy(precision, l.block, &bpc, gen);
+        const hipError_t oe = batch ? fk::batch_occupancy(precision, l.block, &bpc, loop, shared)
+                                    : fk::walk_occupancy(precision, l.block, &bpc, loop);
         if (oe != hipSuccess || bpc <= 0)
             return fail(FK_EDEVICE, "occupancy query failed for block %d", l.block);
     }
@@ -423,7 +427,7 @@ fk_status solve(int32_t kind, const double* stations, int64_t n_stations, const 
     char* ws = static_cast<char*>(workspace);
 
     fk::LaunchCfg cfg;
-    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, general_loop(p))) != FK_OK) return st;
+    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p))) != FK_OK) return st;
 
     fk::WalkCommon C;
     fill_common(C, kind, stations, n_stations, box, p, L, ws);
@@ -543,8 +547,8 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
     const int precision = probs[0].params.precision;
 
     fk::LaunchCfg cfg;
-    bool gen = false;
-    for (int32_t m = 0; m < n; ++m) gen = gen || general_loop(&probs[m].params);
+    int loop = 0;
+    for (int32_t m = 0; m < n; ++m) loop = std::max(loop, loop_kind(&probs[m].params));
     // one source for the whole batch (e.g. u and g_z of one model): the walk
     // kernel then reads it from its arguments instead of per-lane descriptors
     fk::BatchArgs A;
@@ -565,7 +569,7 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
             shared = std::memcmp(&o, &A.src32, sizeof o) == 0;
         }
     }
-    if ((st = plan_launch(precision, BL.n_tasks, &cfg, true, gen, shared)) != FK_OK) return st;
+    if ((st = plan_launch(precision, BL.n_tasks, &cfg, true, loop, shared)) != FK_OK) return st;
 
     std::vector<int64_t> task_off(n + 1, 0), block_off(n + 1, 0);
     int64_t station_base = 0;
@@ -617,7 +621,7 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
 
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     const bool timed = timing_begin(&ev, stream);
-    e = fk::launch_batch_walk(A, cfg, stream, gen, shared);
+    e = fk::launch_batch_walk(A, cfg, stream, loop, shared);
     if (timed) timing_end(ev, stream);
     if (e != hipSuccess) return fail(FK_EDEVICE, "batch walk launch failed: %s", hipGetErrorString(e));
     e = fk::launch_batch_reduce(A, BL.n_blocks, BL.n_stations, stream);
@@ -674,7 +678,7 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
     int64_t* counts = reinterpret_cast<int64_t*>(ws + AL.counts);
 
     fk::LaunchCfg cfg;
-    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, general_loop(p))) != FK_OK) return st;
+    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p))) != FK_OK) return st;
     fk::WalkCommon C;
     fill_common(C, kind, stations, n_stations, box, p, L, nullptr);
     C.exits = nullptr;
@@ -866,7 +870,7 @@ fk_status fk_autotune(int32_t kind, const double* stations, int64_t n_stations, 
     st = FK_OK;
     for (int bi = 0; bi < 3 && st == FK_OK; ++bi) {
         int occ = 0;
-        if (fk::walk_occupancy(precision, blocks[bi], &occ, general_loop(params)) != hipSuccess || occ <= 0)
+        if (fk::walk_occupancy(precision, blocks[bi], &occ, loop_kind(params)) != hipSuccess || occ <= 0)
             continue;
         const int bpcs[2] = {0, occ > 1 ? occ / 2 : 1};
         for (int pi = 0; pi < 2 && st == FK_OK; ++pi) {

@@ -192,8 +192,9 @@ hipError_t launch_fill_zero(int64_t* p, int64_t n, hipStream_t stream);
 hipError_t launch_adjoint_combine(const int64_t* counts, int64_t n_stations, int64_t nvox, const double* grad_out,
                                   const fk_stat* fwd, double scale, double* grad_rho, hipStream_t stream);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream);
-// gen: the general stepping loop (ball domain or Brownian-bridge test)
-hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, bool gen = false);
+// loop: 0 box stepping loop, 1 with the ball exit test, 2 with the
+// Brownian-bridge test too
+hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop = 0);
 hipError_t launch_stream_blocks(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
                                 double* z64, float* z32, hipStream_t stream);
 
@@ -201,8 +202,8 @@ hipError_t launch_stream_blocks(const uint32_t* ctr, int64_t n, uint32_t key0, u
 // captured graph replays it), the persistent walk kernel over all problems,
 // and the batched reduction.
 hipError_t launch_write_words(uint64_t* dst, const uint64_t* host_words, int64_t n_words, hipStream_t stream);
-hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, bool gen, bool shared);
+hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, int loop, bool shared);
 hipError_t launch_batch_reduce(const BatchArgs& a, int64_t n_blocks, int64_t n_station_threads, hipStream_t stream);
-hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, bool gen = false, bool shared = false);
+hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, int loop = 0, bool shared = false);
 
 }  // namespace fk

@@ -317,9 +317,10 @@ struct LaneProblem {
 };
 
 // One lane's walk.
-// GEN: the general stepping loop (ball domain, Brownian-bridge test);
-// without it the loop is the box domain's with the step-end exit test only.
-template <bool F64, bool KAHAN, bool ADJ, bool GEN>
+// LOOP: 0 = the box domain's stepping loop with the step-end exit test only;
+// 1 = with the ball domain's exit test; 2 = also with the Brownian-bridge
+// test.  A launch uses the least general loop its problems need.
+template <bool F64, bool KAHAN, bool ADJ, int LOOP>
 struct Walker {
     using T = typename Prec<F64>::T;
     uint64_t task;
@@ -398,14 +399,14 @@ struct Walker {
         n += 1;
         bool out;
         T d2 = T(0);
-        if (GEN && P.ball) {
+        if (LOOP >= 1 && P.ball) {
             d2 = dist2(y0, y1, y2, P.lo0, P.lo1, P.lo2);
             out = d2 >= P.hi0;
         } else {
             out = y0 <= P.lo0 || y0 >= P.hi0 || y1 <= P.lo1 || y1 >= P.hi1 || y2 <= P.lo2 || y2 >= P.hi2;
         }
         int stop = -1;
-        if (GEN && P.bridge && !out) {
+        if (LOOP == 2 && P.bridge && !out) {
             const bool deep_y = deep_inside(P, y0, y1, y2, d2);
             if (!(deep && deep_y)) stop = bridge_stop(P, n - 1, y0, y1, y2);
             deep = deep_y;
@@ -437,7 +438,7 @@ struct Walker {
         } else {
             const WalkCommon& C = *P.C;
             double e[3] = {0.0, 0.0, 0.0};
-            if (GEN && how >= 2) {
+            if (LOOP == 2 && how >= 2) {
                 // bridge stop: the step's end projected onto the face
                 e[0] = (double)e0;
                 e[1] = (double)e1;
@@ -474,7 +475,7 @@ struct Walker {
 // ---------------------------------------------------------------------------
 // The kernel body.
 // ---------------------------------------------------------------------------
-template <bool F64, bool KAHAN, bool ADJ, bool BATCH, bool GEN, bool SHARED, class Args>
+template <bool F64, bool KAHAN, bool ADJ, bool BATCH, int LOOP, bool SHARED, class Args>
 __device__ __forceinline__ void walk_body(const Args& A)
 {
     using T = typename Prec<F64>::T;
@@ -513,7 +514,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
         else return *P.src;
     };
     Pool pool{0ull, 0ull, Q.n_tasks, false};
-    Walker<F64, KAHAN, ADJ, GEN> W;
+    Walker<F64, KAHAN, ADJ, LOOP> W;
     W.active = false;
     W.task = 0;
     W.x0 = W.x1 = W.x2 = W.rp = T(0);
@@ -573,7 +574,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
                     W.rp = Prec<F64>::rho(source(), W.x0, W.x1, W.x2);
                 }
                 W.deep = false;
-                if (GEN && P.bridge) {
+                if (LOOP == 2 && P.bridge) {
                     const T d2 = P.ball ? dist2(W.x0, W.x1, W.x2, P.lo0, P.lo1, P.lo2) : T(0);
                     W.deep = W.deep_inside(P, W.x0, W.x1, W.x2, d2);
                 }
@@ -682,7 +683,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
 #endif
 // Batches (box loop): 4 blocks for FP64 (128 VGPRs, no spill) and 5 for
 // mixed precision (96 VGPRs, a 12-byte spill) measured 7-10 % faster than the
-// unconstrained 3 and 4.  The general loop (ball, bridge) is left free.
+// unconstrained 3 and 4.  The ball and bridge loops are left free.
 #ifndef FK_BATCH_F64_BLOCKS_PER_CU
 #define FK_BATCH_F64_BLOCKS_PER_CU 4
 #endif
@@ -690,18 +691,18 @@ __device__ __forceinline__ void walk_body(const Args& A)
 #define FK_BATCH_F32_BLOCKS_PER_CU 5
 #endif
 
-template <bool F64, bool KAHAN, bool ADJ, bool GEN>
+template <bool F64, bool KAHAN, bool ADJ, int LOOP>
 __global__ void __launch_bounds__(256, F64 ? FK_F64_BLOCKS_PER_CU : FK_F32_BLOCKS_PER_CU)
     walk_kernel(const typename std::conditional<F64, WalkArgsF64, WalkArgsF32>::type A)
 {
-    walk_body<F64, KAHAN, ADJ, false, GEN, false>(A);
+    walk_body<F64, KAHAN, ADJ, false, LOOP, false>(A);
 }
 
-template <bool F64, bool KAHAN, bool GEN, bool SHARED>
-__global__ void __launch_bounds__(256, GEN ? 1 : F64 ? FK_BATCH_F64_BLOCKS_PER_CU : FK_BATCH_F32_BLOCKS_PER_CU)
+template <bool F64, bool KAHAN, int LOOP, bool SHARED>
+__global__ void __launch_bounds__(256, LOOP ? 1 : F64 ? FK_BATCH_F64_BLOCKS_PER_CU : FK_BATCH_F32_BLOCKS_PER_CU)
     batch_walk_kernel(const BatchArgs A)
 {
-    walk_body<F64, KAHAN, false, true, GEN, SHARED>(A);
+    walk_body<F64, KAHAN, false, true, LOOP, SHARED>(A);
 }
 
 }  // namespace
@@ -714,45 +715,65 @@ hipError_t launch_zero_queue(unsigned long long* queue, hipStream_t stream)
 
 namespace {
 
-bool general(const WalkCommon& c) { return c.domain == FK_DOMAIN_BALL || c.exit_rule == FK_EXIT_BRIDGE; }
+int loop_of(const WalkCommon& c)
+{
+    return c.exit_rule == FK_EXIT_BRIDGE ? 2 : c.domain == FK_DOMAIN_BALL ? 1 : 0;
+}
 
 template <bool F64, bool KAHAN, bool ADJ, class A>
 void launch_walk(const A& a, const LaunchCfg& cfg, hipStream_t stream)
 {
-    if (general(a.c))
-        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, true>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
-    else
-        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, false>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+    switch (loop_of(a.c)) {
+    case 2:
+        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, 2>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+        break;
+    case 1:
+        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, 1>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+        break;
+    default:
+        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, 0>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
+    }
 }
 
-template <bool GEN>
+template <int LOOP>
 const void* walk_fn(int precision)
 {
-    return precision == FK_F64 ? (const void*)walk_kernel<true, false, false, GEN>
-         : precision == FK_MIXED_KAHAN ? (const void*)walk_kernel<false, true, false, GEN>
-                                       : (const void*)walk_kernel<false, false, false, GEN>;
+    return precision == FK_F64 ? (const void*)walk_kernel<true, false, false, LOOP>
+         : precision == FK_MIXED_KAHAN ? (const void*)walk_kernel<false, true, false, LOOP>
+                                       : (const void*)walk_kernel<false, false, false, LOOP>;
 }
 
-template <bool GEN, bool SHARED>
+template <int LOOP, bool SHARED>
 const void* batch_fn(int precision)
 {
-    return precision == FK_F64 ? (const void*)batch_walk_kernel<true, false, GEN, SHARED>
-         : precision == FK_MIXED_KAHAN ? (const void*)batch_walk_kernel<false, true, GEN, SHARED>
-                                       : (const void*)batch_walk_kernel<false, false, GEN, SHARED>;
+    return precision == FK_F64 ? (const void*)batch_walk_kernel<true, false, LOOP, SHARED>
+         : precision == FK_MIXED_KAHAN ? (const void*)batch_walk_kernel<false, true, LOOP, SHARED>
+                                       : (const void*)batch_walk_kernel<false, false, LOOP, SHARED>;
 }
 
-template <bool GEN, bool SHARED>
+template <int LOOP, bool SHARED>
 void launch_batch(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream)
 {
     if (a.precision == FK_F64)
-        hipLaunchKernelGGL((batch_walk_kernel<true, false, GEN, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0, stream,
+        hipLaunchKernelGGL((batch_walk_kernel<true, false, LOOP, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0, stream,
                            a);
     else if (a.precision == FK_MIXED_KAHAN)
-        hipLaunchKernelGGL((batch_walk_kernel<false, true, GEN, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0,
+        hipLaunchKernelGGL((batch_walk_kernel<false, true, LOOP, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0,
                            stream, a);
     else
-        hipLaunchKernelGGL((batch_walk_kernel<false, false, GEN, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0,
+        hipLaunchKernelGGL((batch_walk_kernel<false, false, LOOP, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0,
                            stream, a);
+}
+
+template <bool SHARED>
+void launch_batch_loop(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, int loop)
+{
+    if (loop == 2)
+        launch_batch<2, SHARED>(a, cfg, stream);
+    else if (loop == 1)
+        launch_batch<1, SHARED>(a, cfg, stream);
+    else
+        launch_batch<0, SHARED>(a, cfg, stream);
 }
 
 }  // namespace
@@ -782,25 +803,30 @@ hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cf
     return hipGetLastError();
 }
 
-hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, bool gen)
+hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop)
 {
-    const void* fn = gen ? walk_fn<true>(precision) : walk_fn<false>(precision);
+    const void* fn = loop == 2 ? walk_fn<2>(precision) : loop == 1 ? walk_fn<1>(precision) : walk_fn<0>(precision);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
-hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, bool gen, bool shared)
+hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, int loop, bool shared)
 {
-    if (gen)
-        shared ? launch_batch<true, true>(a, cfg, stream) : launch_batch<true, false>(a, cfg, stream);
+    if (shared)
+        launch_batch_loop<true>(a, cfg, stream, loop);
     else
-        shared ? launch_batch<false, true>(a, cfg, stream) : launch_batch<false, false>(a, cfg, stream);
+        launch_batch_loop<false>(a, cfg, stream, loop);
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, bool gen, bool shared)
+hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, int loop, bool shared)
 {
-    const void* fn = gen ? (shared ? batch_fn<true, true>(precision) : batch_fn<true, false>(precision))
-                         : (shared ? batch_fn<false, true>(precision) : batch_fn<false, false>(precision));
+    const void* fn;
+    if (shared)
+        fn = loop == 2 ? batch_fn<2, true>(precision) : loop == 1 ? batch_fn<1, true>(precision)
+                                                      : batch_fn<0, true>(precision);
+    else
+        fn = loop == 2 ? batch_fn<2, false>(precision) : loop == 1 ? batch_fn<1, false>(precision)
+                                                       : batch_fn<0, false>(precision);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
