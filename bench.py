@@ -52,19 +52,21 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 62.91, "box_muller_pair_f64": 94.30, "box_muller_pair_f32": 20.48,
-              "step_f64": 29.40, "step_f32_f64sum": 25.02}
+ISSUE_COST = {"philox_block": 63.84, "box_muller_pair_f64": 94.39, "box_muller_pair_f32": 20.46,
+              "step_f64": 29.50, "step_f32_f64sum": 25.06}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
-# over the u and g_z launches), each scaled by what the same counter reads for
+# over the launches of each form), each scaled by what the same counter reads for
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "db727111cc75d50ede5d9981815b163afde21b59549cfe82fce1fb03b7099c8d",
+    "sources_sha256": "a7f1423c1067f0d1a59f249622ec147f91503fb01ed41a1004fffa69769ee472",
     "fetch_scale": 1.9998838968923347, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 197.75, "write_kib": 890324.90625},
-    "f64_separate": {"fetch_kib": 220.59375, "write_kib": 438656.40625},
+    "f64_batched": {"fetch_kib": 11392.0625, "write_kib": 960288.3125},
+    "f64_separate": {"fetch_kib": 212.546875, "write_kib": 438721.125},
+    "mixed_batched": {"fetch_kib": 164.21875, "write_kib": 929111.015625},
+    "mixed_separate": {"fetch_kib": 158.765625, "write_kib": 474760.7109375},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")
@@ -370,27 +372,33 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="bat
 
     if precision_name == "f64":
         # the same pass in the other launch form, and the mixed-precision
-        # kernel (its faster form: two launches) -- outside the timed region
+        # kernel in both forms -- outside the timed region
         other = "separate" if mode == "batched" else "batched"
         ostep, ostats = make_stepper(prob, other)
         oel, _ = timed(ostep, K, 1)
         result["f64_" + other] = {"value": steps_per_pass * K / oel, "unit": "Brownian steps/s"}
         pmix = prob.replace(precision=W.PREC_MIXED_F64ACC)
-        mstep, mstats = make_stepper(pmix, "separate")
-        mel, _ = timed(mstep, K, 1)
+        mstep, mstats = make_stepper(pmix, "batched")
+        mel, mwalk_ms = timed(mstep, K, 1, walk_timing=True)
         mu, mg = mstats()
         msteps = int(mu["sum_steps"].sum()) + int(mg["sum_steps"].sum())
         mval = msteps * K / mel
-        bstep, _ = make_stepper(pmix, "batched")
-        bel, _ = timed(bstep, K, 1)
+        sstep, _ = make_stepper(pmix, "separate")
+        sel, _ = timed(sstep, K, 1)
         # the two kernels draw different normals (FP32 and FP64 streams), so
         # their estimates are independent: differences are scaled by the
         # standard error of the difference, sqrt(se_a^2 + se_b^2)
         du = float(np.max(np.abs(mu["mean"] - su["mean"]) / np.hypot(mu["se"], su["se"])))
         dg = float(np.max(np.abs(mg["mean"] - sg["mean"]) / np.hypot(mg["se"], sg["se"])))
-        result["mixed"] = {"value": mval, "unit": "Brownian steps/s", "launch": "separate",
+        mach = msteps * K * algorithmic_ops_per_step("mixed") / (sum(mwalk_ms) * 1e-3) / 1e12
+        result["mixed"] = {"value": mval, "unit": "Brownian steps/s", "launch": "batched",
                            "speedup_vs_f64": mval / value,
-                           "batched_value": msteps * K / bel,
+                           "roofline": {"bound": "alu", "achieved": mach, "peak": peak, "unit": "T lane-slots/s",
+                                        "frac": mach / peak, "traffic": measured_traffic("mixed", "batched"),
+                                        "kernel": "batch_walk_kernel<F32, F64 sum>",
+                                        "ops_per_step": algorithmic_ops_per_step("mixed"),
+                                        "kernel_avg_ms": float(np.mean(mwalk_ms))},
+                           "separate_value": msteps * K / sel,
                            "max_abs_diff_vs_f64_in_combined_se": {"u": du, "g_z": dg}}
 
     if want_paper:

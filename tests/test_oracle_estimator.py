@@ -10,6 +10,8 @@ what the mathematics fixes, at any time step:
 * the uniform ball and the SI prism against their closed forms;
 * g_z by common-random-number central differences against the difference of
   the closed form;
+* agreement within 4 standard errors on disjoint walk blocks of growing size,
+  with the standard error halving per fourfold size;
 * mean step counts against the exact expected exit time of a box;
 * occupation counts (the adjoint) against the linearity of u in rho.
 """
@@ -169,6 +171,25 @@ def test_standard_error_scales_as_inverse_sqrt_n():
     s16 = oracle.solve(pr, 0)[0][0]["se"]
     s4 = oracle.solve(pr, 0, n_paths=4000)[0][0]["se"]
     assert s4 / s16 == pytest.approx(2.0, rel=0.12)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_agreement_within_4_se_as_the_walk_count_grows(kind):
+    pr = W.cfg1(16000).replace(stations=W.cfg1().stations[[1, 5]])
+    h = math.sqrt(pr.dt)
+    zc = np.array([x[2] for x in pr.stations])
+    M = pr.bc_data[3]
+    target = -M / zc if kind == 0 else M / (zc * zc - h * h)
+    prev = None
+    for n in (1000, 4000, 16000, 64000):
+        # disjoint walk blocks, so each size is an independent estimate
+        stats = oracle.solve(pr.replace(path_offset=n), kind, n_paths=n)[0]
+        z = _zscores(stats, target)
+        assert np.all(np.abs(z) < 4.0), (n, z)
+        se = np.array([s["se"] for s in stats])
+        if prev is not None:
+            assert np.all(np.abs(prev / se / 2.0 - 1.0) < 0.2), prev / se
+        prev = se
 
 
 def test_path_offset_resumes_the_same_streams():
