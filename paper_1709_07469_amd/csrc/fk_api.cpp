@@ -366,10 +366,18 @@ void fill_source_f32(fk::SourceF32& S, const fk_source* s)
         for (int c = 0; c < 5; ++c) S.spheres[j][c] = (float)s->spheres[5 * j + c];
 }
 
-// The stepping loop a problem needs: 0 box, 1 ball exit test, 2 bridge test.
-int loop_kind(const fk_params* p)
+// The stepping loop a problem needs: 0 box, 1 ball exit test, 2 bridge test;
+// plus 4 when its source has a voxel grid (the loop then loads grid values
+// ahead).  A batch takes the most general exit test and the grid bit of any.
+int loop_kind(const fk_params* p, const fk_source* s)
 {
-    return p->exit_rule == FK_EXIT_BRIDGE ? 2 : p->domain == FK_DOMAIN_BALL ? 1 : 0;
+    const int e = p->exit_rule == FK_EXIT_BRIDGE ? 2 : p->domain == FK_DOMAIN_BALL ? 1 : 0;
+    return e | (s && s->rho ? 4 : 0);
+}
+
+int merge_loops(int a, int b)
+{
+    return std::max(a & 3, b & 3) | ((a | b) & 4);
 }
 
 fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false, int loop = 0,
@@ -427,7 +435,7 @@ fk_status solve(int32_t kind, const double* stations, int64_t n_stations, const 
     char* ws = static_cast<char*>(workspace);
 
     fk::LaunchCfg cfg;
-    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p))) != FK_OK) return st;
+    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p, src))) != FK_OK) return st;
 
     fk::WalkCommon C;
     fill_common(C, kind, stations, n_stations, box, p, L, ws);
@@ -548,7 +556,7 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
 
     fk::LaunchCfg cfg;
     int loop = 0;
-    for (int32_t m = 0; m < n; ++m) loop = std::max(loop, loop_kind(&probs[m].params));
+    for (int32_t m = 0; m < n; ++m) loop = merge_loops(loop, loop_kind(&probs[m].params, &probs[m].source));
     // one source for the whole batch (e.g. u and g_z of one model): the walk
     // kernel then reads it from its arguments instead of per-lane descriptors
     fk::BatchArgs A;
@@ -678,7 +686,7 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
     int64_t* counts = reinterpret_cast<int64_t*>(ws + AL.counts);
 
     fk::LaunchCfg cfg;
-    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p))) != FK_OK) return st;
+    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p, nullptr))) != FK_OK) return st;
     fk::WalkCommon C;
     fill_common(C, kind, stations, n_stations, box, p, L, nullptr);
     C.exits = nullptr;
@@ -870,7 +878,7 @@ fk_status fk_autotune(int32_t kind, const double* stations, int64_t n_stations, 
     st = FK_OK;
     for (int bi = 0; bi < 3 && st == FK_OK; ++bi) {
         int occ = 0;
-        if (fk::walk_occupancy(precision, blocks[bi], &occ, loop_kind(params)) != hipSuccess || occ <= 0)
+        if (fk::walk_occupancy(precision, blocks[bi], &occ, loop_kind(params, source)) != hipSuccess || occ <= 0)
             continue;
         const int bpcs[2] = {0, occ > 1 ? occ / 2 : 1};
         for (int pi = 0; pi < 2 && st == FK_OK; ++pi) {

@@ -295,11 +295,16 @@ __device__ __forceinline__ double bodies_f64(const SourceF64& s, double r, doubl
     return r;
 }
 
-__device__ __forceinline__ double rho_f64(const SourceF64& s, double x, double y, double z)
+// The voxel grid's density at (x, y, z): zero outside the grid or without one.
+__device__ __forceinline__ double grid_f64(const SourceF64& s, double x, double y, double z)
 {
     const int64_t v = voxel_f64(s, x, y, z);
-    const double r = v >= 0 ? 0.0 + (double)s.rho[v] : 0.0;
-    return bodies_f64(s, r, x, y, z);
+    return v >= 0 ? 0.0 + (double)s.rho[v] : 0.0;
+}
+
+__device__ __forceinline__ double rho_f64(const SourceF64& s, double x, double y, double z)
+{
+    return bodies_f64(s, grid_f64(s, x, y, z), x, y, z);
 }
 
 __device__ __forceinline__ int voxel_f32(const SourceF32& s, float x, float y, float z)
@@ -326,11 +331,15 @@ __device__ __forceinline__ float bodies_f32(const SourceF32& s, float r, float x
     return r;
 }
 
-__device__ __forceinline__ float rho_f32(const SourceF32& s, float x, float y, float z)
+__device__ __forceinline__ float grid_f32(const SourceF32& s, float x, float y, float z)
 {
     const int v = voxel_f32(s, x, y, z);
-    const float r = v >= 0 ? 0.0f + s.rho[v] : 0.0f;
-    return bodies_f32(s, r, x, y, z);
+    return v >= 0 ? 0.0f + s.rho[v] : 0.0f;
+}
+
+__device__ __forceinline__ float rho_f32(const SourceF32& s, float x, float y, float z)
+{
+    return bodies_f32(s, grid_f32(s, x, y, z), x, y, z);
 }
 
 // ---------------------------------------------------------------------------

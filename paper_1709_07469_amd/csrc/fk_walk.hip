@@ -190,6 +190,15 @@ struct Scatter {
 template <bool F64>
 struct Prec;
 
+// x, from here on held in a vector register (an empty asm with a vector
+// operand: no instruction is emitted)
+template <class T>
+__device__ __forceinline__ T in_vgpr(T x)
+{
+    asm("" : "+v"(x));
+    return x;
+}
+
 template <>
 struct Prec<true> {
     using T = double;
@@ -199,6 +208,8 @@ struct Prec<true> {
     __device__ static void normals(const Block& b, T* z, const BmTables* t) { normals_f64(b, *t, z[0], z[1]); }
     __device__ static T fmat(T a, T b, T c) { return fma(a, b, c); }
     __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f64(s, x, y, z); }
+    __device__ static T grid(const Src& s, T x, T y, T z) { return grid_f64(s, x, y, z); }
+    __device__ static T bodies(const Src& s, T g, T x, T y, T z) { return bodies_f64(s, g, x, y, z); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f64(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo[c]; }
     __device__ static T hi(const WalkCommon& C, int c) { return C.hi[c]; }
@@ -229,6 +240,8 @@ struct Prec<false> {
     }
     __device__ static T fmat(T a, T b, T c) { return fmaf(a, b, c); }
     __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f32(s, x, y, z); }
+    __device__ static T grid(const Src& s, T x, T y, T z) { return grid_f32(s, x, y, z); }
+    __device__ static T bodies(const Src& s, T g, T x, T y, T z) { return bodies_f32(s, g, x, y, z); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f32(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo_f[c]; }
     __device__ static T hi(const WalkCommon& C, int c) { return C.hi_f[c]; }
@@ -316,10 +329,16 @@ struct LaneProblem {
     }
 };
 
+// The stepping loop a kernel instance is built for.  Bits 0-1: 0 = the box
+// domain's loop with the step-end exit test only; 1 = with the ball domain's
+// exit test; 2 = also with the Brownian-bridge test.  Bit 2: the density
+// source has a voxel grid, whose values each macro-step loads ahead.  A launch
+// uses the least general loop its problems need.
+constexpr int kLoopGrid = 4;
+constexpr int loop_exit(int loop) { return loop & 3; }
+constexpr bool loop_grid(int loop) { return (loop & kLoopGrid) != 0; }
+
 // One lane's walk.
-// LOOP: 0 = the box domain's stepping loop with the step-end exit test only;
-// 1 = with the ball domain's exit test; 2 = also with the Brownian-bridge
-// test.  A launch uses the least general loop its problems need.
 template <bool F64, bool KAHAN, bool ADJ, int LOOP>
 struct Walker {
     using T = typename Prec<F64>::T;
@@ -372,19 +391,38 @@ struct Walker {
         return U <= T(1) - keep ? fbest : -1;
     }
 
-    // One Euler-Maruyama step with normals (z0, z1, z2).  Returns true when
-    // the walk ends here, with how = 0: it left the domain (a = last inside
+    // Turns the normals of the next MACRO steps into the points those steps
+    // reach (as if none ended the walk) and, with a grid, loads the grid
+    // density at each, all loads issued before the first is used.  Points past
+    // the walk's end are never used.
+    __device__ __forceinline__ void advance(const LaneProblem<F64>& P, const typename Prec<F64>::Src& src, T* z,
+                                            T* g) const
+    {
+        constexpr int MACRO = Prec<F64>::kMacro;
+        T p0 = x0, p1 = x1, p2 = x2;
+#pragma unroll
+        for (int s = 0; s < MACRO; ++s) {
+            p0 = Prec<F64>::fmat(P.sdt, z[3 * s], p0);
+            p1 = Prec<F64>::fmat(P.sdt, z[3 * s + 1], p1);
+            p2 = Prec<F64>::fmat(P.sdt, z[3 * s + 2], p2);
+            z[3 * s] = p0;
+            z[3 * s + 1] = p1;
+            z[3 * s + 2] = p2;
+            g[s] = (ADJ || !loop_grid(LOOP)) ? T(0) : Prec<F64>::grid(src, p0, p1, p2);
+        }
+    }
+
+    // One Euler-Maruyama step, to (y0, y1, y2) = x + sqrt(dt) z (advance).
+    // Returns true when the walk ends here, with how = 0: it left the domain (a = last inside
     // point, e = the first point outside); how = 1: it reached max_steps;
     // how = 2 + f: the bridge test stopped it at face f (e = the step's end).
-    __device__ __forceinline__ bool step(const LaneProblem<F64>& P, const typename Prec<F64>::Src& src, T z0, T z1,
-                                         T z2, T& a0, T& a1, T& a2, T& e0, T& e1, T& e2, int& how)
+    // g is the grid density at the step's end.
+    __device__ __forceinline__ bool step(const LaneProblem<F64>& P, const typename Prec<F64>::Src& src, T y0, T y1,
+                                         T y2, T g, T& a0, T& a1, T& a2, T& e0, T& e1, T& e2, int& how)
     {
-        const T y0 = Prec<F64>::fmat(P.sdt, z0, x0);
-        const T y1 = Prec<F64>::fmat(P.sdt, z1, x1);
-        const T y2 = Prec<F64>::fmat(P.sdt, z2, x2);
         T rn = T(0);
         if (!ADJ) {
-            rn = Prec<F64>::rho(src, y0, y1, y2);
+            rn = Prec<F64>::bodies(src, g, y0, y1, y2);
             if (F64) {
                 S = S + (double)(rp + rn);
             } else if (KAHAN) {
@@ -399,14 +437,14 @@ struct Walker {
         n += 1;
         bool out;
         T d2 = T(0);
-        if (LOOP >= 1 && P.ball) {
+        if (loop_exit(LOOP) >= 1 && P.ball) {
             d2 = dist2(y0, y1, y2, P.lo0, P.lo1, P.lo2);
             out = d2 >= P.hi0;
         } else {
             out = y0 <= P.lo0 || y0 >= P.hi0 || y1 <= P.lo1 || y1 >= P.hi1 || y2 <= P.lo2 || y2 >= P.hi2;
         }
         int stop = -1;
-        if (LOOP == 2 && P.bridge && !out) {
+        if (loop_exit(LOOP) == 2 && P.bridge && !out) {
             const bool deep_y = deep_inside(P, y0, y1, y2, d2);
             if (!(deep && deep_y)) stop = bridge_stop(P, n - 1, y0, y1, y2);
             deep = deep_y;
@@ -438,7 +476,7 @@ struct Walker {
         } else {
             const WalkCommon& C = *P.C;
             double e[3] = {0.0, 0.0, 0.0};
-            if (LOOP == 2 && how >= 2) {
+            if (loop_exit(LOOP) == 2 && how >= 2) {
                 // bridge stop: the step's end projected onto the face
                 e[0] = (double)e0;
                 e[1] = (double)e1;
@@ -505,6 +543,16 @@ __device__ __forceinline__ void walk_body(const Args& A)
     } else {
         Q = Queue{A.c.queue, (uint64_t)A.c.n_tasks, (uint32_t)A.c.grab, A.c.total_waves};
         P.load(A.c, A.src);
+        // held in vector registers, as a batch holds them: kept in scalar
+        // registers beside the source's bodies they overflow the scalar file,
+        // and every step then reloads them from spill lanes
+        P.sdt = in_vgpr(P.sdt);
+        P.lo0 = in_vgpr(P.lo0);
+        P.lo1 = in_vgpr(P.lo1);
+        P.lo2 = in_vgpr(P.lo2);
+        P.hi0 = in_vgpr(P.hi0);
+        P.hi1 = in_vgpr(P.hi1);
+        P.hi2 = in_vgpr(P.hi2);
     }
     // the density source of the lane's walk: the launch's (kernel arguments),
     // the batch's shared one (kernel arguments), or the lane's problem's
@@ -574,7 +622,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
                     W.rp = Prec<F64>::rho(source(), W.x0, W.x1, W.x2);
                 }
                 W.deep = false;
-                if (LOOP == 2 && P.bridge) {
+                if (loop_exit(LOOP) == 2 && P.bridge) {
                     const T d2 = P.ball ? dist2(W.x0, W.x1, W.x2, P.lo0, P.lo1, P.lo2) : T(0);
                     W.deep = W.deep_inside(P, W.x0, W.x1, W.x2, d2);
                 }
@@ -636,11 +684,13 @@ __device__ __forceinline__ void walk_body(const Args& A)
                         const int q = 3 * s0 + c;
                         zz[c] = tail_z[wave][(q / NPB) * m + rank][q % NPB];
                     }
+                    T g[MACRO];
+                    W.advance(P, source(), zz, g);
 #pragma unroll
                     for (int s = 0; s < MACRO; ++s) {
                         if (!done)
-                            done = W.step(P, source(), zz[3 * s], zz[3 * s + 1], zz[3 * s + 2], a0, a1, a2, e0, e1, e2,
-                                          how);
+                            done = W.step(P, source(), zz[3 * s], zz[3 * s + 1], zz[3 * s + 2], g[s], a0, a1, a2, e0,
+                                          e1, e2, how);
                     }
                 }
                 W.k += (uint32_t)B;
@@ -663,9 +713,12 @@ __device__ __forceinline__ void walk_body(const Args& A)
         bool done = false;
         int how = 0;
         T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
+        T g[MACRO];
+        W.advance(P, source(), z, g);
 #pragma unroll
         for (int s = 0; s < MACRO; ++s) {
-            if (!done) done = W.step(P, source(), z[3 * s], z[3 * s + 1], z[3 * s + 2], a0, a1, a2, e0, e1, e2, how);
+            if (!done)
+                done = W.step(P, source(), z[3 * s], z[3 * s + 1], z[3 * s + 2], g[s], a0, a1, a2, e0, e1, e2, how);
         }
         if (done) W.finish(P, a0, a1, a2, e0, e1, e2, how);
     }
@@ -678,8 +731,10 @@ __device__ __forceinline__ void walk_body(const Args& A)
 #ifndef FK_F64_BLOCKS_PER_CU
 #define FK_F64_BLOCKS_PER_CU 4
 #endif
+// Mixed-precision walks are held to 6 (80 VGPRs): the grid loop's prefetched
+// densities would otherwise take the compiler to 85 VGPRs and 5 wavefronts.
 #ifndef FK_F32_BLOCKS_PER_CU
-#define FK_F32_BLOCKS_PER_CU 1
+#define FK_F32_BLOCKS_PER_CU 6
 #endif
 // Batches (box loop): 4 blocks for FP64 (128 VGPRs, no spill) and 5 for
 // mixed precision (96 VGPRs, a 12-byte spill) measured 7-10 % faster than the
@@ -699,7 +754,7 @@ __global__ void __launch_bounds__(256, F64 ? FK_F64_BLOCKS_PER_CU : FK_F32_BLOCK
 }
 
 template <bool F64, bool KAHAN, int LOOP, bool SHARED>
-__global__ void __launch_bounds__(256, LOOP ? 1 : F64 ? FK_BATCH_F64_BLOCKS_PER_CU : FK_BATCH_F32_BLOCKS_PER_CU)
+__global__ void __launch_bounds__(256, loop_exit(LOOP) ? 1 : F64 ? FK_BATCH_F64_BLOCKS_PER_CU : FK_BATCH_F32_BLOCKS_PER_CU)
     batch_walk_kernel(const BatchArgs A)
 {
     walk_body<F64, KAHAN, false, true, LOOP, SHARED>(A);
@@ -715,24 +770,29 @@ hipError_t launch_zero_queue(unsigned long long* queue, hipStream_t stream)
 
 namespace {
 
-int loop_of(const WalkCommon& c)
+// Calls f with the loop variant as a compile-time constant.
+template <class F>
+void with_loop(int loop, F&& f)
 {
-    return c.exit_rule == FK_EXIT_BRIDGE ? 2 : c.domain == FK_DOMAIN_BALL ? 1 : 0;
+    switch (loop) {
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    default: f(std::integral_constant<int, 0>{});
+    }
 }
 
+// The adjoint samples no density (it counts voxel visits), so its loop never
+// carries the grid bit.
 template <bool F64, bool KAHAN, bool ADJ, class A>
-void launch_walk(const A& a, const LaunchCfg& cfg, hipStream_t stream)
+void launch_walk(const A& a, int loop, const LaunchCfg& cfg, hipStream_t stream)
 {
-    switch (loop_of(a.c)) {
-    case 2:
-        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, 2>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
-        break;
-    case 1:
-        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, 1>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
-        break;
-    default:
-        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, 0>), dim3(cfg.grid), dim3(cfg.block), 0, stream, a);
-    }
+    with_loop(ADJ ? loop_exit(loop) : loop, [&](auto L) {
+        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, decltype(L)::value>), dim3(cfg.grid), dim3(cfg.block), 0,
+                           stream, a);
+    });
 }
 
 template <int LOOP>
@@ -765,68 +825,66 @@ void launch_batch(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream)
                            stream, a);
 }
 
-template <bool SHARED>
-void launch_batch_loop(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, int loop)
+// The loop variant of a single problem's launch (see loop_exit, loop_grid).
+int loop_of(const WalkCommon& c, bool grid)
 {
-    if (loop == 2)
-        launch_batch<2, SHARED>(a, cfg, stream);
-    else if (loop == 1)
-        launch_batch<1, SHARED>(a, cfg, stream);
-    else
-        launch_batch<0, SHARED>(a, cfg, stream);
+    const int e = c.exit_rule == FK_EXIT_BRIDGE ? 2 : c.domain == FK_DOMAIN_BALL ? 1 : 0;
+    return e | (grid ? kLoopGrid : 0);
 }
 
 }  // namespace
 
 hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream_t stream, bool adjoint)
 {
+    const int loop = loop_of(a.c, a.src.has_grid != 0);
     if (adjoint)
-        launch_walk<true, false, true>(a, cfg, stream);
+        launch_walk<true, false, true>(a, loop, cfg, stream);
     else
-        launch_walk<true, false, false>(a, cfg, stream);
+        launch_walk<true, false, false>(a, loop, cfg, stream);
     return hipGetLastError();
 }
 
 hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cfg, hipStream_t stream, bool adjoint)
 {
+    const int loop = loop_of(a.c, a.src.has_grid != 0);
     if (adjoint) {
         if (kahan)
-            launch_walk<false, true, true>(a, cfg, stream);
+            launch_walk<false, true, true>(a, loop, cfg, stream);
         else
-            launch_walk<false, false, true>(a, cfg, stream);
+            launch_walk<false, false, true>(a, loop, cfg, stream);
     } else {
         if (kahan)
-            launch_walk<false, true, false>(a, cfg, stream);
+            launch_walk<false, true, false>(a, loop, cfg, stream);
         else
-            launch_walk<false, false, false>(a, cfg, stream);
+            launch_walk<false, false, false>(a, loop, cfg, stream);
     }
     return hipGetLastError();
 }
 
 hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop)
 {
-    const void* fn = loop == 2 ? walk_fn<2>(precision) : loop == 1 ? walk_fn<1>(precision) : walk_fn<0>(precision);
+    const void* fn = nullptr;
+    with_loop(loop, [&](auto L) { fn = walk_fn<decltype(L)::value>(precision); });
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
 hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, int loop, bool shared)
 {
-    if (shared)
-        launch_batch_loop<true>(a, cfg, stream, loop);
-    else
-        launch_batch_loop<false>(a, cfg, stream, loop);
+    with_loop(loop, [&](auto L) {
+        if (shared)
+            launch_batch<decltype(L)::value, true>(a, cfg, stream);
+        else
+            launch_batch<decltype(L)::value, false>(a, cfg, stream);
+    });
     return hipGetLastError();
 }
 
 hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, int loop, bool shared)
 {
-    const void* fn;
-    if (shared)
-        fn = loop == 2 ? batch_fn<2, true>(precision) : loop == 1 ? batch_fn<1, true>(precision)
-                                                      : batch_fn<0, true>(precision);
-    else
-        fn = loop == 2 ? batch_fn<2, false>(precision) : loop == 1 ? batch_fn<1, false>(precision)
-                                                       : batch_fn<0, false>(precision);
+    const void* fn = nullptr;
+    with_loop(loop, [&](auto L) {
+        fn = shared ? batch_fn<decltype(L)::value, true>(precision) : batch_fn<decltype(L)::value, false>(precision);
+    });
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
