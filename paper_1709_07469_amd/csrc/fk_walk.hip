@@ -41,9 +41,20 @@ namespace {
 constexpr uint32_t kCapFlag = 0x80000000u;
 constexpr int kMaxWaves = 4;        // 256 threads per block at most
 
+// In a batch of problems with separate sources the task queue is split into
+// kStripes contiguous stripes with a claim counter each (the queue slot of a
+// workspace holds 32 counters).  Block b starts on stripe b mod kStripes --
+// consecutive blocks are placed on the 8 XCDs in turn, so each XCD walks its
+// own contiguous range of tasks and its wavefronts hold walks of one problem
+// at a time (the problem-uniform fast path applies, and an XCD's L2 serves
+// one problem's grid) -- and a wavefront whose stripe runs out takes the
+// next.  Other launches keep one counter: their lanes share a source anyway,
+// and stripes that end on long walks lengthen the drain.
+constexpr uint32_t kStripes = 8;
+
 __global__ void zero_queue_kernel(unsigned long long* q)
 {
-    if (threadIdx.x == 0) q[0] = 0ull;
+    if (threadIdx.x < kStripes) q[threadIdx.x] = 0ull;
 }
 
 __device__ __forceinline__ uint64_t first_lane_u64(uint64_t v)
@@ -60,9 +71,9 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Wave-uniform claim state over the global task queue.
+// Wave-uniform claim state over the striped task queue.
 struct Queue {
-    unsigned long long* counter;
+    unsigned long long* counter;   // one claim counter per stripe
     uint64_t n_tasks;
     uint32_t grab;
     uint32_t total_waves;
@@ -71,29 +82,43 @@ struct Queue {
 struct Pool {
     uint64_t next, end, left;
     bool exhausted;
+    uint32_t stripe, tried;
 };
 
+template <uint32_t STRIPES>
+__device__ __forceinline__ Pool start_pool(const Queue& Q)
+{
+    return Pool{0ull, 0ull, Q.n_tasks, false, blockIdx.x % STRIPES, 0u};
+}
+
 // Refills idle lanes from the wavefront's claimed run, claiming a new run
-// when it is empty.  Returns the task of this lane if it was idle and got
+// from its stripe when it is empty (and moving to the next stripe when that
+// one is used up).  Returns the task of this lane if it was idle and got
 // one, else ~0.
+template <uint32_t STRIPES>
 __device__ __forceinline__ uint64_t refill(Pool& pool, const Queue& Q, bool active)
 {
     const uint64_t idle = __ballot(!active);
     if (idle == 0) return ~0ull;
     const uint32_t n_idle = (uint32_t)__popcll(idle);
-    if (pool.next == pool.end && !pool.exhausted) {
+    // each pass claims a run or uses up one stripe: STRIPES passes at most
+    for (uint32_t pass = 0; pass < STRIPES && pool.next == pool.end && !pool.exhausted; ++pass) {
+        const uint64_t lo = Q.n_tasks * pool.stripe / STRIPES;
+        const uint64_t hi = Q.n_tasks * (pool.stripe + 1) / STRIPES;
         uint64_t want = pool.left / (4ull * Q.total_waves);
         if (want < n_idle) want = n_idle;
         if (want > (uint64_t)Q.grab) want = (uint64_t)Q.grab;
         unsigned long long old = 0ull;
-        if (__lane_id() == 0) old = atomicAdd(Q.counter, (unsigned long long)want);
+        if (__lane_id() == 0) old = atomicAdd(Q.counter + pool.stripe, (unsigned long long)want);
         old = first_lane_u64(__shfl(old, 0));
-        if (old >= Q.n_tasks) {
+        if (old < hi - lo) {
+            pool.next = lo + old;
+            pool.end = lo + old + want < hi ? lo + old + want : hi;
+            pool.left = (hi - pool.end) * STRIPES;   // the whole queue's, estimated
+        } else if (STRIPES == 1 || ++pool.tried == STRIPES) {
             pool.exhausted = true;
         } else {
-            pool.next = old;
-            pool.end = old + want < Q.n_tasks ? old + want : Q.n_tasks;
-            pool.left = Q.n_tasks - pool.end;
+            pool.stripe = (pool.stripe + 1) % STRIPES;
         }
     }
     const uint64_t avail = pool.end - pool.next;
@@ -281,9 +306,25 @@ __device__ __forceinline__ const typename std::conditional<F64, SourceF64, Sourc
         return A.src32;
 }
 
+// The lanes' common source when every live lane of the wavefront points at
+// the same one (a wavefront claims consecutive walks, so it almost always
+// works on one problem), re-addressed through the constant address space so
+// that its fields load with scalar instructions into scalar registers; null
+// when the lanes' problems differ.  Called with only the live lanes active.
+template <class Src>
+__device__ __forceinline__ const Src* wave_uniform(const Src* p)
+{
+    const uint64_t a = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+    const uint64_t f = ((uint64_t)hi << 32) | lo;
+    if (!__all(a == f)) return nullptr;
+    return (const Src*)(const __attribute__((address_space(4))) Src*)f;
+}
+
 // Stepping parameters of the problem a lane is walking.  In single-problem
-// launches they are the same for every lane (held in scalar registers); in a
-// batch each lane loads its problem's at the start of a walk.
+// launches they are the same for every lane; in a batch each lane loads its
+// problem's at the start of a walk.
 template <bool F64>
 struct LaneProblem {
     using T = typename Prec<F64>::T;
@@ -561,7 +602,21 @@ __device__ __forceinline__ void walk_body(const Args& A)
         else if constexpr (SHARED) return shared_source<F64>(A);
         else return *P.src;
     };
-    Pool pool{0ull, 0ull, Q.n_tasks, false};
+    // runs f on the source of the live lanes' walks (called with only those
+    // lanes active): in a batch of separate sources, through wave_uniform when
+    // the wavefront's walks share one
+    auto with_source = [&](auto&& f) {
+        if constexpr (BATCH && !SHARED) {
+            if (const auto* u = wave_uniform(P.src))
+                f(*u);
+            else
+                f(*P.src);
+        } else {
+            f(source());
+        }
+    };
+    constexpr uint32_t STRIPES = (BATCH && !SHARED) ? kStripes : 1u;
+    Pool pool = start_pool<STRIPES>(Q);
     Walker<F64, KAHAN, ADJ, LOOP> W;
     W.active = false;
     W.task = 0;
@@ -575,7 +630,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
     const int lane = (int)__lane_id();
 
     for (;;) {
-        const uint64_t got = refill(pool, Q, W.active);
+        const uint64_t got = refill<STRIPES>(pool, Q, W.active);
         if (got != ~0ull) {
             const WalkCommon* Cp;
             uint64_t t = got;
@@ -684,14 +739,16 @@ __device__ __forceinline__ void walk_body(const Args& A)
                         const int q = 3 * s0 + c;
                         zz[c] = tail_z[wave][(q / NPB) * m + rank][q % NPB];
                     }
-                    T g[MACRO];
-                    W.advance(P, source(), zz, g);
+                    with_source([&](const typename Prec<F64>::Src& src) {
+                        T g[MACRO];
+                        W.advance(P, src, zz, g);
 #pragma unroll
-                    for (int s = 0; s < MACRO; ++s) {
-                        if (!done)
-                            done = W.step(P, source(), zz[3 * s], zz[3 * s + 1], zz[3 * s + 2], g[s], a0, a1, a2, e0,
-                                          e1, e2, how);
-                    }
+                        for (int s = 0; s < MACRO; ++s) {
+                            if (!done)
+                                done = W.step(P, src, zz[3 * s], zz[3 * s + 1], zz[3 * s + 2], g[s], a0, a1, a2, e0,
+                                              e1, e2, how);
+                        }
+                    });
                 }
                 W.k += (uint32_t)B;
                 if (done) W.finish(P, a0, a1, a2, e0, e1, e2, how);
@@ -713,13 +770,15 @@ __device__ __forceinline__ void walk_body(const Args& A)
         bool done = false;
         int how = 0;
         T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
-        T g[MACRO];
-        W.advance(P, source(), z, g);
+        with_source([&](const typename Prec<F64>::Src& src) {
+            T g[MACRO];
+            W.advance(P, src, z, g);
 #pragma unroll
-        for (int s = 0; s < MACRO; ++s) {
-            if (!done)
-                done = W.step(P, source(), z[3 * s], z[3 * s + 1], z[3 * s + 2], g[s], a0, a1, a2, e0, e1, e2, how);
-        }
+            for (int s = 0; s < MACRO; ++s) {
+                if (!done)
+                    done = W.step(P, src, z[3 * s], z[3 * s + 1], z[3 * s + 2], g[s], a0, a1, a2, e0, e1, e2, how);
+            }
+        });
         if (done) W.finish(P, a0, a1, a2, e0, e1, e2, how);
     }
 }

@@ -44,6 +44,27 @@ def test_batch_equals_standalone_bitwise(precision):
         assert np.array_equal(bv.view(np.uint64), av.view(np.uint64)) and np.array_equal(bs, as_)
 
 
+@pytest.mark.parametrize("walks", [(2, 3), (2, 5, 4), (7, 2, 3, 9)])
+def test_tiny_batches_of_separate_sources_equal_standalone(walks):
+    """Batches of problems with their own sources split the queue into
+    stripes; with fewer walks than stripes most stripes are empty or hold one
+    walk, and every walk must still run exactly once."""
+    from paper_1709_07469_amd import fkgrav as F
+    c1 = W.cfg1(2)
+    models = W.cfg4(n_models=len(walks), n=16)
+    probs, kinds = [], []
+    for j, n in enumerate(walks):
+        base = c1 if j == 0 else models[j].replace(precision=W.PREC_F64)
+        probs.append(base.replace(paths_per_station=max(n, 2), stations=base.stations[:1], problem_id=60 + j))
+        kinds.append(j % 2)
+    say("tiny batch walks", walks)
+    res, ws, PB, _ = F.solve_batch(probs, kinds)
+    for m, (p, k) in enumerate(zip(probs, kinds)):
+        alone, _, _ = F.solve(p, k)
+        assert res[m].tobytes() == alone.tobytes(), (m, res[m], alone)
+        assert res[m]["n"][0] + res[m]["n_trunc"][0] == p.paths_per_station
+
+
 def test_batch_f64_matches_oracle_walk_by_walk():
     from paper_1709_07469_amd import fkgrav as F
     probs, kinds = _small_mix(W.PREC_F64)
