@@ -52,8 +52,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 63.84, "box_muller_pair_f64": 94.39, "box_muller_pair_f32": 20.46,
-              "step_f64": 29.50, "step_f32_f64sum": 25.06}
+ISSUE_COST = {"philox_block": 64.73, "box_muller_pair_f64": 95.19, "box_muller_pair_f32": 20.50,
+              "step_f64": 29.46, "step_f32_f64sum": 25.04}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -61,12 +61,12 @@ ISSUE_COST = {"philox_block": 63.84, "box_muller_pair_f64": 94.39, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "a7f1423c1067f0d1a59f249622ec147f91503fb01ed41a1004fffa69769ee472",
-    "fetch_scale": 1.9998838968923347, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 11392.0625, "write_kib": 960288.3125},
-    "f64_separate": {"fetch_kib": 212.546875, "write_kib": 438721.125},
-    "mixed_batched": {"fetch_kib": 164.21875, "write_kib": 929111.015625},
-    "mixed_separate": {"fetch_kib": 158.765625, "write_kib": 474760.7109375},
+    "sources_sha256": "43ec04c1c438f4db8877f99896220936cfd72e9f8532ae1fb65dc4e20697c927",
+    "fetch_scale": 1.9998796058653638, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 179.3125, "write_kib": 877666.46875},
+    "f64_separate": {"fetch_kib": 170.171875, "write_kib": 442865.40625},
+    "mixed_batched": {"fetch_kib": 154.1875, "write_kib": 927548.1875},
+    "mixed_separate": {"fetch_kib": 141.75, "write_kib": 474686.046875},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")
