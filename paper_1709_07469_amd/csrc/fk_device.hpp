@@ -295,11 +295,31 @@ __device__ __forceinline__ double bodies_f64(const SourceF64& s, double r, doubl
     return r;
 }
 
-// The voxel grid's density at (x, y, z): zero outside the grid or without one.
+// The voxel grid's density at (x, y, z): zero outside the grid or without one
+// (the same voxel as voxel_f64).  Branch-free, so that several lookups can be
+// in flight at once: each floored coordinate t is clamped into [0, n-1] --
+// t lies in the grid exactly when the clamp leaves it unchanged (t is an
+// integer; a NaN never compares equal) -- and the load always reads a voxel
+// of the grid, its value dropped outside.  The host limits a grid to 2^31 - 1
+// voxels, so the flat index fits 32 bits.
+// grid_in_* need a grid (has_grid); grid_* check for one.
+__device__ __forceinline__ double grid_in_f64(const SourceF64& s, double x, double y, double z)
+{
+    const double tx = grid_axis_f64(x, s.origin[0], s.spacing[0], s.inv[0], s.exact[0]);
+    const double ty = grid_axis_f64(y, s.origin[1], s.spacing[1], s.inv[1], s.exact[1]);
+    const double tz = grid_axis_f64(z, s.origin[2], s.spacing[2], s.inv[2], s.exact[2]);
+    const double cx = fmin(fmax(tx, 0.0), (double)(s.n[0] - 1));
+    const double cy = fmin(fmax(ty, 0.0), (double)(s.n[1] - 1));
+    const double cz = fmin(fmax(tz, 0.0), (double)(s.n[2] - 1));
+    const bool in = (cx == tx) & (cy == ty) & (cz == tz);
+    const uint32_t v = ((uint32_t)cz * (uint32_t)s.n[1] + (uint32_t)cy) * (uint32_t)s.n[0] + (uint32_t)cx;
+    const float r = s.rho[v];
+    return in ? 0.0 + (double)r : 0.0;
+}
+
 __device__ __forceinline__ double grid_f64(const SourceF64& s, double x, double y, double z)
 {
-    const int64_t v = voxel_f64(s, x, y, z);
-    return v >= 0 ? 0.0 + (double)s.rho[v] : 0.0;
+    return s.has_grid ? grid_in_f64(s, x, y, z) : 0.0;
 }
 
 __device__ __forceinline__ double rho_f64(const SourceF64& s, double x, double y, double z)
@@ -331,10 +351,25 @@ __device__ __forceinline__ float bodies_f32(const SourceF32& s, float r, float x
     return r;
 }
 
+// FP32 stepping's grid lookup, branch-free like grid_f64 (the same voxel as
+// voxel_f32).
+__device__ __forceinline__ float grid_in_f32(const SourceF32& s, float x, float y, float z)
+{
+    const float tx = floorf((x - s.origin[0]) * s.inv[0]);
+    const float ty = floorf((y - s.origin[1]) * s.inv[1]);
+    const float tz = floorf((z - s.origin[2]) * s.inv[2]);
+    const float cx = fminf(fmaxf(tx, 0.0f), s.nf[0] - 1.0f);
+    const float cy = fminf(fmaxf(ty, 0.0f), s.nf[1] - 1.0f);
+    const float cz = fminf(fmaxf(tz, 0.0f), s.nf[2] - 1.0f);
+    const bool in = (cx == tx) & (cy == ty) & (cz == tz);
+    const uint32_t v = ((uint32_t)cz * (uint32_t)s.n[1] + (uint32_t)cy) * (uint32_t)s.n[0] + (uint32_t)cx;
+    const float r = s.rho[v];
+    return in ? 0.0f + r : 0.0f;
+}
+
 __device__ __forceinline__ float grid_f32(const SourceF32& s, float x, float y, float z)
 {
-    const int v = voxel_f32(s, x, y, z);
-    return v >= 0 ? 0.0f + s.rho[v] : 0.0f;
+    return s.has_grid ? grid_in_f32(s, x, y, z) : 0.0f;
 }
 
 __device__ __forceinline__ float rho_f32(const SourceF32& s, float x, float y, float z)

@@ -233,7 +233,7 @@ struct Prec<true> {
     __device__ static void normals(const Block& b, T* z, const BmTables* t) { normals_f64(b, *t, z[0], z[1]); }
     __device__ static T fmat(T a, T b, T c) { return fma(a, b, c); }
     __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f64(s, x, y, z); }
-    __device__ static T grid(const Src& s, T x, T y, T z) { return grid_f64(s, x, y, z); }
+    __device__ static T grid_in(const Src& s, T x, T y, T z) { return grid_in_f64(s, x, y, z); }
     __device__ static T bodies(const Src& s, T g, T x, T y, T z) { return bodies_f64(s, g, x, y, z); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f64(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo[c]; }
@@ -265,7 +265,7 @@ struct Prec<false> {
     }
     __device__ static T fmat(T a, T b, T c) { return fmaf(a, b, c); }
     __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f32(s, x, y, z); }
-    __device__ static T grid(const Src& s, T x, T y, T z) { return grid_f32(s, x, y, z); }
+    __device__ static T grid_in(const Src& s, T x, T y, T z) { return grid_in_f32(s, x, y, z); }
     __device__ static T bodies(const Src& s, T g, T x, T y, T z) { return bodies_f32(s, g, x, y, z); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f32(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo_f[c]; }
@@ -449,7 +449,14 @@ struct Walker {
             z[3 * s] = p0;
             z[3 * s + 1] = p1;
             z[3 * s + 2] = p2;
-            g[s] = (ADJ || !loop_grid(LOOP)) ? T(0) : Prec<F64>::grid(src, p0, p1, p2);
+            g[s] = T(0);
+        }
+        // A launch takes the grid loop when any of its problems has a grid,
+        // but a batch may mix sources with and without one: the lane's own
+        // source is checked, once for all the macro-step's loads.
+        if (!ADJ && loop_grid(LOOP) && src.has_grid) {
+#pragma unroll
+            for (int s = 0; s < MACRO; ++s) g[s] = Prec<F64>::grid_in(src, z[3 * s], z[3 * s + 1], z[3 * s + 2]);
         }
     }
 
@@ -790,8 +797,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
 #ifndef FK_F64_BLOCKS_PER_CU
 #define FK_F64_BLOCKS_PER_CU 4
 #endif
-// Mixed-precision walks are held to 6 (80 VGPRs): the grid loop's prefetched
-// densities would otherwise take the compiler to 85 VGPRs and 5 wavefronts.
+// Mixed-precision walks are held to 6 (80 VGPRs).
 #ifndef FK_F32_BLOCKS_PER_CU
 #define FK_F32_BLOCKS_PER_CU 6
 #endif
@@ -805,15 +811,31 @@ __device__ __forceinline__ void walk_body(const Args& A)
 #define FK_BATCH_F32_BLOCKS_PER_CU 5
 #endif
 
+// Grid loops keep several grid loads in flight, which takes registers: mixed
+// single-problem walks measured best at 5 blocks (96 VGPRs), mixed batches of
+// separate sources at 4 (128 VGPRs; per-lane source fields), while a batch
+// sharing one source stays at 5.
+#ifndef FK_F32_GRID_BLOCKS_PER_CU
+#define FK_F32_GRID_BLOCKS_PER_CU 5
+#endif
+#ifndef FK_BATCH_F32_GRID_BLOCKS_PER_CU
+#define FK_BATCH_F32_GRID_BLOCKS_PER_CU 4
+#endif
+
 template <bool F64, bool KAHAN, bool ADJ, int LOOP>
-__global__ void __launch_bounds__(256, F64 ? FK_F64_BLOCKS_PER_CU : FK_F32_BLOCKS_PER_CU)
+__global__ void __launch_bounds__(256, F64                ? FK_F64_BLOCKS_PER_CU
+                                       : loop_grid(LOOP) ? FK_F32_GRID_BLOCKS_PER_CU
+                                                         : FK_F32_BLOCKS_PER_CU)
     walk_kernel(const typename std::conditional<F64, WalkArgsF64, WalkArgsF32>::type A)
 {
     walk_body<F64, KAHAN, ADJ, false, LOOP, false>(A);
 }
 
 template <bool F64, bool KAHAN, int LOOP, bool SHARED>
-__global__ void __launch_bounds__(256, loop_exit(LOOP) ? 1 : F64 ? FK_BATCH_F64_BLOCKS_PER_CU : FK_BATCH_F32_BLOCKS_PER_CU)
+__global__ void __launch_bounds__(256, loop_exit(LOOP)   ? 1
+                                       : F64             ? FK_BATCH_F64_BLOCKS_PER_CU
+                                       : (loop_grid(LOOP) && !SHARED) ? FK_BATCH_F32_GRID_BLOCKS_PER_CU
+                                                                      : FK_BATCH_F32_BLOCKS_PER_CU)
     batch_walk_kernel(const BatchArgs A)
 {
     walk_body<F64, KAHAN, false, true, LOOP, SHARED>(A);
