@@ -16,12 +16,13 @@ walk kernel, station estimates per second at fixed relative standard error,
 the mixed-precision kernel on the same workload, the paper's Table 1
 workload (its experiment 1 at every time step and walk count, next to the
 K20Xm times it reports), the 32-model batched workload in one graph-captured
-launch (default and autotuned launch settings), and the CPU oracle timed on
-a bounded sample on the host.
+launch (default and autotuned launch settings), the adjoint d g_z / d rho on
+a voxel workload next to its forward solve, and the CPU oracle timed on a
+bounded sample on the host.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64|mixed]
                   [--launch batched|separate] [--no-cpu-baseline] [--cpu-seconds S]
-                  [--no-paper-table] [--no-batched-models]
+                  [--no-paper-table] [--no-batched-models] [--no-adjoint]
 """
 from __future__ import annotations
 
@@ -322,7 +323,58 @@ def batched_models():
                       "launch": {k: tuned[k] for k in ("block", "blocks_per_cu", "grab")}}}
 
 
-def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="batched", want_models=True):
+def adjoint_leg(reps=2):
+    """d g_z / d rho on the voxel workload (32^3 FP32 grid of 5 prisms, 32
+    stations, 1e6 common-random-number walk pairs, zero data, FP64): the
+    forward g_z solve and the adjoint replay of the same walks (occupation
+    counts and their combination into one gradient), each timed with events
+    over `reps` runs after one warm-up."""
+    import numpy as np
+    import torch
+
+    from paper_1709_07469_amd import fkgrav as F
+    from paper_1709_07469_amd import workloads as W
+
+    pr = W.cfg5()
+    P = F.Prepared(pr)
+    S = pr.n_stations
+    ws = F.alloc_workspace(F.fk_workspace_bytes(1, S, P.params))
+    out = F.alloc_stats(S)
+    g = torch.full((S,), 1.0 / S, dtype=torch.float64, device=P.stations.device)
+    grad = torch.empty(int(np.asarray(pr.rho).size), dtype=torch.float64, device=P.stations.device)
+    aws = F.alloc_workspace(F.fk_adjoint_workspace_bytes(S, P.source))
+
+    def forward():
+        F.fk_solve_gz(P.stations, P.box, P.source, P.bc, P.params, out, ws)
+
+    def backward():
+        F.fk_gz_adjoint(P.stations, P.box, P.source, P.bc, P.params, out, ws, g, grad, aws)
+
+    def seconds(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    t_fwd = seconds(forward)
+    steps = int(F.stats_to_numpy(out)[:S]["sum_steps"].sum())
+    t_adj = seconds(backward)
+    del ws, aws
+    torch.cuda.empty_cache()
+    return {"workload": "d(mean g_z)/d rho: 32^3 FP32 grid of 5 prisms, 32 stations, 1e6 CRN walk pairs, zero data, "
+                        "FP64; the adjoint replays the forward walks and scatters their trapezoid weights per voxel",
+            "voxels": int(np.asarray(pr.rho).size), "steps": steps,
+            "forward_seconds": t_fwd, "forward_steps_per_s": steps / t_fwd,
+            "adjoint_seconds": t_adj, "adjoint_steps_per_s": steps / t_adj, "adjoint_over_forward": t_adj / t_fwd}
+
+
+def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="batched", want_models=True,
+        want_adjoint=True):
     import numpy as np
 
     from paper_1709_07469_amd import workloads as W
@@ -403,6 +455,8 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="bat
 
     if want_paper:
         result["paper_table1"] = paper_table1(precision_name)
+    if want_adjoint and precision_name == "f64":
+        result["adjoint"] = adjoint_leg()
     if want_models and precision_name == "f64":
         result["batched_models"] = batched_models()
     if want_cpu:
@@ -421,6 +475,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-table", action="store_true", help="skip the paper's Table 1 workload")
     ap.add_argument("--no-batched-models", action="store_true", help="skip the 32-model batched workload")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one device-to-device copy of this many bytes (calibrates HBM byte counters)")
@@ -435,7 +490,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     res = run(a.precision, max(1, a.steps), max(0, a.warmup), a.cpu_seconds, not a.no_cpu_baseline,
-              not a.no_paper_table, a.launch, not a.no_batched_models)
+              not a.no_paper_table, a.launch, not a.no_batched_models, not a.no_adjoint)
     if a.copy_bytes > 0:
         src = torch.ones(a.copy_bytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

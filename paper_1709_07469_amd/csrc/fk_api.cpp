@@ -381,7 +381,7 @@ int merge_loops(int a, int b)
 }
 
 fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false, int loop = 0,
-                      bool shared = false)
+                      bool shared = false, bool adjoint = false)
 {
     fk_launch l;
     {
@@ -395,7 +395,7 @@ fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool b
     int bpc = l.blocks_per_cu;
     if (bpc <= 0) {
         const hipError_t oe = batch ? fk::batch_occupancy(precision, l.block, &bpc, loop, shared)
-                                    : fk::walk_occupancy(precision, l.block, &bpc, loop);
+                                    : fk::walk_occupancy(precision, l.block, &bpc, loop, adjoint);
         if (oe != hipSuccess || bpc <= 0)
             return fail(FK_EDEVICE, "occupancy query failed for block %d", l.block);
     }
@@ -686,7 +686,8 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
     int64_t* counts = reinterpret_cast<int64_t*>(ws + AL.counts);
 
     fk::LaunchCfg cfg;
-    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p, nullptr))) != FK_OK) return st;
+    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p, nullptr), false, true)) != FK_OK)
+        return st;
     fk::WalkCommon C;
     fill_common(C, kind, stations, n_stations, box, p, L, nullptr);
     C.exits = nullptr;

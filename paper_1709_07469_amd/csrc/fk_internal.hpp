@@ -194,7 +194,7 @@ hipError_t launch_adjoint_combine(const int64_t* counts, int64_t n_stations, int
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream);
 // loop: 0 box stepping loop, 1 with the ball exit test, 2 with the
 // Brownian-bridge test too
-hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop = 0);
+hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop = 0, bool adjoint = false);
 hipError_t launch_stream_blocks(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
                                 double* z64, float* z32, hipStream_t stream);
 

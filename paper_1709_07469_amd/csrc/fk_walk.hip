@@ -188,15 +188,74 @@ __device__ __forceinline__ bool forward_capped(const WalkCommon& C, uint64_t t)
     return (C.fwd_steps[t] & kCapFlag) != 0;
 }
 
-// Run-length coalesced scatter of signed trapezoid weights (adjoint).
+// The adjoint's signed trapezoid weights are gathered in a block-shared LDS
+// table before they reach the global int64 counts.  A walk crosses a voxel
+// face on most steps of a fine grid, and every global atomic on device memory
+// is performed at the memory side (hundreds of cycles, limited in flight), so
+// the walks of a block -- which start from the same stations and crowd the
+// same voxels -- first add into the table.  Each slot is one 64-bit word,
+// (index + 1) << 32 | int32 count, updated by compare-and-swap only, so it is
+// atomic across the block's wavefronts; a different index evicts the slot's
+// entry to the global counts, and counts that would leave +-2^30 go there
+// directly.  The table is flushed when the block's walks are done.  Integer
+// sums in any order: the counts are exact and the same as without the table.
+#ifndef FK_ADJ_TABLE_BITS
+#define FK_ADJ_TABLE_BITS 12
+#endif
+constexpr int kAdjTableBits = FK_ADJ_TABLE_BITS;
+constexpr int kAdjSlots = 1 << kAdjTableBits;   // 12 bits: 32 KiB of LDS per block
+
+__device__ __forceinline__ void global_add(int64_t* counts, int64_t idx, int64_t w)
+{
+    atomicAdd(reinterpret_cast<unsigned long long*>(counts + idx), (unsigned long long)w);
+}
+
+__device__ __forceinline__ void adj_emit(unsigned long long* tab, int64_t* counts, int64_t idx, int64_t w)
+{
+    constexpr int64_t kBound = 1ll << 30;
+    if ((uint64_t)idx >= 0xFFFFFFFEull || w >= kBound || w <= -kBound) {
+        global_add(counts, idx, w);
+        return;
+    }
+    const uint32_t k1 = (uint32_t)idx + 1u;
+    const uint32_t slot = ((uint32_t)idx * 2654435761u) >> (32 - kAdjTableBits);
+    unsigned long long cur = __hip_atomic_load(&tab[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (;;) {
+        const uint32_t ck = (uint32_t)(cur >> 32);
+        const int64_t cc = (int32_t)(uint32_t)cur;
+        int64_t keep = w, out_idx = -1, out_c = 0;   // out: what leaves the table if this swap wins
+        if (ck == k1) {
+            keep = cc + w;
+            if (keep >= kBound || keep <= -kBound) {
+                out_idx = idx;
+                out_c = keep;
+                keep = 0;
+            }
+        } else if (ck != 0) {
+            out_idx = (int64_t)ck - 1;
+            out_c = cc;
+        }
+        const unsigned long long want = ((unsigned long long)k1 << 32) | (uint32_t)(int32_t)keep;
+        const unsigned long long prev = atomicCAS(&tab[slot], cur, want);
+        if (prev == cur) {
+            if (out_c != 0) global_add(counts, out_idx, out_c);
+            return;
+        }
+        cur = prev;
+    }
+}
+
+// Run-length coalesced scatter of one walk's signed trapezoid weights.
 struct Scatter {
-    int64_t* base;   // counts of this walk's station
-    int64_t v;       // pending voxel (-1: none)
-    int64_t c;       // pending weight
+    int64_t* counts;            // the problem's counts
+    unsigned long long* tab;    // the block's table
+    int64_t row;                // station offset into counts
+    int64_t v;                  // pending voxel (-1: none)
+    int64_t c;                  // pending weight
     int64_t sign;
     __device__ __forceinline__ void flush()
     {
-        if (v >= 0 && c != 0) atomicAdd(reinterpret_cast<unsigned long long*>(base + v), (unsigned long long)c);
+        if (v >= 0 && c != 0) adj_emit(tab, counts, row + v, c);
         c = 0;
     }
     __device__ __forceinline__ void add(int64_t voxel, int64_t weight)
@@ -632,7 +691,15 @@ __device__ __forceinline__ void walk_body(const Args& A)
     W.Sf = W.Sc = 0.0f;
     W.n = W.k = W.sctr = W.pctr = 0;
     W.deep = false;
-    W.sc = Scatter{nullptr, -1, 0, 1};
+    W.sc = Scatter{nullptr, nullptr, 0, -1, 0, 1};
+    unsigned long long* adj_tab = nullptr;
+    if constexpr (ADJ) {
+        static_assert(!BATCH, "the adjoint runs single-problem launches");
+        __shared__ unsigned long long tab[kAdjSlots];
+        for (int i = threadIdx.x; i < kAdjSlots; i += blockDim.x) tab[i] = 0ull;
+        __syncthreads();
+        adj_tab = tab;
+    }
     const int wave = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
 
@@ -675,7 +742,9 @@ __device__ __forceinline__ void walk_body(const Args& A)
                 W.S = 0.0;
                 W.Sf = W.Sc = 0.0f;
                 if (ADJ) {
-                    W.sc.base = C.counts + ti.s * C.nvox;
+                    W.sc.counts = C.counts;
+                    W.sc.tab = adj_tab;
+                    W.sc.row = (int64_t)ti.s * C.nvox;
                     W.sc.v = -1;
                     W.sc.c = 0;
                     W.sc.sign = ti.w ? -1 : 1;
@@ -788,6 +857,15 @@ __device__ __forceinline__ void walk_body(const Args& A)
         });
         if (done) W.finish(P, a0, a1, a2, e0, e1, e2, how);
     }
+    if constexpr (ADJ) {
+        // every wavefront has left the loop: the table's entries go out
+        __syncthreads();
+        for (int i = threadIdx.x; i < kAdjSlots; i += blockDim.x) {
+            const unsigned long long e = adj_tab[i];
+            const int64_t c = (int32_t)(uint32_t)e;
+            if ((e >> 32) != 0 && c != 0) global_add(A.c.counts, (int64_t)(e >> 32) - 1, c);
+        }
+    }
 }
 
 // Minimum resident 256-thread blocks per CU the compiler must allow (this
@@ -876,12 +954,12 @@ void launch_walk(const A& a, int loop, const LaunchCfg& cfg, hipStream_t stream)
     });
 }
 
-template <int LOOP>
+template <int LOOP, bool ADJ>
 const void* walk_fn(int precision)
 {
-    return precision == FK_F64 ? (const void*)walk_kernel<true, false, false, LOOP>
-         : precision == FK_MIXED_KAHAN ? (const void*)walk_kernel<false, true, false, LOOP>
-                                       : (const void*)walk_kernel<false, false, false, LOOP>;
+    return precision == FK_F64 ? (const void*)walk_kernel<true, false, ADJ, LOOP>
+         : precision == FK_MIXED_KAHAN ? (const void*)walk_kernel<false, true, ADJ, LOOP>
+                                       : (const void*)walk_kernel<false, false, ADJ, LOOP>;
 }
 
 template <int LOOP, bool SHARED>
@@ -942,10 +1020,13 @@ hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cf
     return hipGetLastError();
 }
 
-hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop)
+hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop, bool adjoint)
 {
     const void* fn = nullptr;
-    with_loop(loop, [&](auto L) { fn = walk_fn<decltype(L)::value>(precision); });
+    if (adjoint)
+        with_loop(loop_exit(loop), [&](auto L) { fn = walk_fn<decltype(L)::value, true>(precision); });
+    else
+        with_loop(loop, [&](auto L) { fn = walk_fn<decltype(L)::value, false>(precision); });
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 
