@@ -53,8 +53,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 64.73, "box_muller_pair_f64": 95.19, "box_muller_pair_f32": 20.50,
-              "step_f64": 29.46, "step_f32_f64sum": 25.04}
+ISSUE_COST = {"philox_block": 60.62, "box_muller_pair_f64": 89.27, "box_muller_pair_f32": 20.27,
+              "step_f64": 29.36, "step_f32_f64sum": 24.91}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -62,12 +62,12 @@ ISSUE_COST = {"philox_block": 64.73, "box_muller_pair_f64": 95.19, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "43ec04c1c438f4db8877f99896220936cfd72e9f8532ae1fb65dc4e20697c927",
-    "fetch_scale": 1.9998796058653638, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 179.3125, "write_kib": 877666.46875},
-    "f64_separate": {"fetch_kib": 170.171875, "write_kib": 442865.40625},
-    "mixed_batched": {"fetch_kib": 154.1875, "write_kib": 927548.1875},
-    "mixed_separate": {"fetch_kib": 141.75, "write_kib": 474686.046875},
+    "sources_sha256": "52536647c6d00169d889195cf56d82eb4db19e282415b04362cee913ff227250",
+    "fetch_scale": 1.999887234370487, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 688.625, "write_kib": 876109.375},
+    "f64_separate": {"fetch_kib": 695.984375, "write_kib": 441017.625},
+    "mixed_batched": {"fetch_kib": 151.21875, "write_kib": 928215.765625},
+    "mixed_separate": {"fetch_kib": 137.28125, "write_kib": 474744.15625},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")

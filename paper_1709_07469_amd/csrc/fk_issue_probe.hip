@@ -212,13 +212,19 @@ int main()
         hipLaunchKernelGGL(it.f, dim3(grid), dim3(block), 0, 0, buf, 1u);
         CHK(hipGetLastError());
         CHK(hipDeviceSynchronize());
-        CHK(hipEventRecord(e0, 0));
-        for (int r = 0; r < 5; ++r) hipLaunchKernelGGL(it.f, dim3(grid), dim3(block), 0, 0, buf, 2u + r);
-        CHK(hipGetLastError());
-        CHK(hipEventRecord(e1, 0));
-        CHK(hipEventSynchronize(e1));
+        // the fastest of 7 timings of 5 launches: the clock drifts by about a
+        // percent between runs, and the part's cost is its best issue rate
         float ms = 0.0f;
-        CHK(hipEventElapsedTime(&ms, e0, e1));
+        for (int t = 0; t < 7; ++t) {
+            CHK(hipEventRecord(e0, 0));
+            for (int r = 0; r < 5; ++r) hipLaunchKernelGGL(it.f, dim3(grid), dim3(block), 0, 0, buf, 2u + r);
+            CHK(hipGetLastError());
+            CHK(hipEventRecord(e1, 0));
+            CHK(hipEventSynchronize(e1));
+            float m = 0.0f;
+            CHK(hipEventElapsedTime(&m, e0, e1));
+            if (t == 0 || m < ms) ms = m;
+        }
         const double units = 5.0 * grid * block * (double)kChains * it.units_per_chain;
         const double slots = slots_per_s * (ms * 1e-3) / units;
         std::printf(", \"%s\": {\"ms\": %.3f, \"slots\": %.3f}", it.name, ms, slots);
