@@ -275,22 +275,28 @@ __device__ __forceinline__ int64_t voxel_f64(const SourceF64& s, double x, doubl
     const double tx = grid_axis_f64(x, s.origin[0], s.spacing[0], s.inv[0], s.exact[0]);
     const double ty = grid_axis_f64(y, s.origin[1], s.spacing[1], s.inv[1], s.exact[1]);
     const double tz = grid_axis_f64(z, s.origin[2], s.spacing[2], s.inv[2], s.exact[2]);
-    const bool in = tx >= 0.0 && tx < (double)s.n[0] && ty >= 0.0 && ty < (double)s.n[1] && tz >= 0.0 &&
-                    tz < (double)s.n[2];
+    // tested without short-circuiting (the bounds load together)
+    const bool in = (tx >= 0.0) & (tx < (double)s.n[0]) & (ty >= 0.0) & (ty < (double)s.n[1]) & (tz >= 0.0) &
+                    (tz < (double)s.n[2]);
     return in ? ((int64_t)(int)tz * s.n[1] + (int)ty) * s.n[0] + (int)tx : -1;
 }
 
 // Density of the analytic bodies at (x, y, z), added to r in body order.
+// The membership tests are combined without short-circuiting and the sum is
+// selected, not branched on: a body's bounds then load together (one wait
+// instead of one per bound) and no lane diverges.
 __device__ __forceinline__ double bodies_f64(const SourceF64& s, double r, double x, double y, double z)
 {
     for (int j = 0; j < s.n_prisms; ++j) {
         const double* q = s.prisms[j];
-        if (x >= q[0] && x < q[3] && y >= q[1] && y < q[4] && z >= q[2] && z < q[5]) r = r + q[6];
+        const bool in = (x >= q[0]) & (x < q[3]) & (y >= q[1]) & (y < q[4]) & (z >= q[2]) & (z < q[5]);
+        r = in ? r + q[6] : r;
     }
     for (int j = 0; j < s.n_spheres; ++j) {
         const double* q = s.spheres[j];
         const double dx = x - q[0], dy = y - q[1], dz = z - q[2];
-        if (dx * dx + dy * dy + dz * dz < q[3] * q[3]) r = r + q[4];
+        const bool in = dx * dx + dy * dy + dz * dz < q[3] * q[3];
+        r = in ? r + q[4] : r;
     }
     return r;
 }
@@ -333,7 +339,7 @@ __device__ __forceinline__ int voxel_f32(const SourceF32& s, float x, float y, f
     const float tx = floorf((x - s.origin[0]) * s.inv[0]);
     const float ty = floorf((y - s.origin[1]) * s.inv[1]);
     const float tz = floorf((z - s.origin[2]) * s.inv[2]);
-    const bool in = tx >= 0.0f && tx < s.nf[0] && ty >= 0.0f && ty < s.nf[1] && tz >= 0.0f && tz < s.nf[2];
+    const bool in = (tx >= 0.0f) & (tx < s.nf[0]) & (ty >= 0.0f) & (ty < s.nf[1]) & (tz >= 0.0f) & (tz < s.nf[2]);
     return in ? ((int)tz * s.n[1] + (int)ty) * s.n[0] + (int)tx : -1;
 }
 
@@ -341,12 +347,14 @@ __device__ __forceinline__ float bodies_f32(const SourceF32& s, float r, float x
 {
     for (int j = 0; j < s.n_prisms; ++j) {
         const float* q = s.prisms[j];
-        if (x >= q[0] && x < q[3] && y >= q[1] && y < q[4] && z >= q[2] && z < q[5]) r = r + q[6];
+        const bool in = (x >= q[0]) & (x < q[3]) & (y >= q[1]) & (y < q[4]) & (z >= q[2]) & (z < q[5]);
+        r = in ? r + q[6] : r;
     }
     for (int j = 0; j < s.n_spheres; ++j) {
         const float* q = s.spheres[j];
         const float dx = x - q[0], dy = y - q[1], dz = z - q[2];
-        if (dx * dx + dy * dy + dz * dz < q[3] * q[3]) r = r + q[4];
+        const bool in = dx * dx + dy * dy + dz * dz < q[3] * q[3];
+        r = in ? r + q[4] : r;
     }
     return r;
 }

@@ -173,8 +173,8 @@ __device__ __forceinline__ TaskInfo decode(const WalkCommon& C, uint64_t t)
 __device__ __forceinline__ bool strictly_inside(const WalkCommon& C, const double x[3])
 {
     if (C.domain == FK_DOMAIN_BALL) return dist2(x[0], x[1], x[2], C.ctr[0], C.ctr[1], C.ctr[2]) < C.r2;
-    return x[0] > C.lo[0] && x[0] < C.hi[0] && x[1] > C.lo[1] && x[1] < C.hi[1] && x[2] > C.lo[2] &&
-           x[2] < C.hi[2];
+    return (x[0] > C.lo[0]) & (x[0] < C.hi[0]) & (x[1] > C.lo[1]) & (x[1] < C.hi[1]) & (x[2] > C.lo[2]) &
+           (x[2] < C.hi[2]);
 }
 
 // Adjoint replay: a walk whose sample (or pair) the forward solve excluded
@@ -677,6 +677,15 @@ __device__ __forceinline__ void walk_body(const Args& A)
                 f(*u);
             else
                 f(*P.src);
+        } else if constexpr (!BATCH) {
+            // the source in the kernel arguments (the launch's one argument,
+            // at the start of the argument segment), re-addressed through an
+            // opaque scalar pointer each macro-step: its bodies are reloaded
+            // with scalar loads instead of being held live (and spilled)
+            // across the loop
+            uint64_t a = (uint64_t)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(Args, src);
+            asm volatile("" : "+s"(a));
+            f(*(const typename Prec<F64>::Src*)(const __attribute__((address_space(4))) typename Prec<F64>::Src*)a);
         } else {
             f(source());
         }
