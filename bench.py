@@ -53,8 +53,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 60.62, "box_muller_pair_f64": 89.27, "box_muller_pair_f32": 20.27,
-              "step_f64": 29.36, "step_f32_f64sum": 24.91}
+ISSUE_COST = {"philox_block": 60.77, "box_muller_pair_f64": 93.33, "box_muller_pair_f32": 20.43,
+              "step_f64": 29.54, "step_f32_f64sum": 25.09}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -62,12 +62,12 @@ ISSUE_COST = {"philox_block": 60.62, "box_muller_pair_f64": 89.27, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "52536647c6d00169d889195cf56d82eb4db19e282415b04362cee913ff227250",
-    "fetch_scale": 1.999887234370487, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 688.625, "write_kib": 876109.375},
-    "f64_separate": {"fetch_kib": 695.984375, "write_kib": 441017.625},
-    "mixed_batched": {"fetch_kib": 151.21875, "write_kib": 928215.765625},
-    "mixed_separate": {"fetch_kib": 137.28125, "write_kib": 474744.15625},
+    "sources_sha256": "61029049d3da9290947c249d84933a71ba62443297dbffd64a2a29b3f0807bc7",
+    "fetch_scale": 1.9998793674755164, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 677.3125, "write_kib": 863036.875},
+    "f64_separate": {"fetch_kib": 693.546875, "write_kib": 435808.0546875},
+    "mixed_batched": {"fetch_kib": 147.96875, "write_kib": 919295.78125},
+    "mixed_separate": {"fetch_kib": 133.765625, "write_kib": 470472.4921875},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")
