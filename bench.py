@@ -437,9 +437,11 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="bat
         mval = msteps * K / mel
         sstep, _ = make_stepper(pmix, "separate")
         sel, _ = timed(sstep, K, 1)
-        # the two kernels draw different normals (FP32 and FP64 streams), so
-        # their estimates are independent: differences are scaled by the
-        # standard error of the difference, sqrt(se_a^2 + se_b^2)
+        # the two kernels turn the same Philox words into different normals
+        # (FP32 and FP64 streams), so their estimates are neither equal nor
+        # independent: differences are scaled by sqrt(se_a^2 + se_b^2), the
+        # standard error of the difference of independent estimates, as a
+        # rough scale only
         zu = (mu["mean"] - su["mean"]) / np.hypot(mu["se"], su["se"])
         zg = (mg["mean"] - sg["mean"]) / np.hypot(mg["se"], sg["se"])
         du, dg = float(np.max(np.abs(zu))), float(np.max(np.abs(zg)))
