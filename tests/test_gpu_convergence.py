@@ -128,3 +128,44 @@ def test_intersect_exit_bias_shrinks_like_sqrt_dt_and_overshoot_has_none():
                 assert np.all(z < -6.0), z
     shrink = rel[1e-3, W.EXIT_INTERSECT] / rel[2.5e-4, W.EXIT_INTERSECT]
     assert np.all((shrink > 1.5) & (shrink < 3.5)), shrink
+
+
+# harmonic h(x) = 0.4 + x - 0.5 y + 0.25 z + 0.2 (x^2 - y^2) + 0.6 xz - 0.2 yz
+# + 0.1 (z^2 - x^2), as (c0, b, A00, A01, A02, A11, A12, A22) with trace 0
+_HARMONIC = np.array([0.4, 1.0, -0.5, 0.25, 0.2, 0.0, 0.3, -0.3, -0.1, 0.1])
+_ST = np.array([[0.0, 0.0, 0.0], [0.5, -0.3, 0.2], [-0.7, 0.6, -0.4], [0.1, 0.85, 0.7]])
+
+
+def _quad(q, x):
+    A = np.array([[q[4], q[5], q[6]], [q[5], q[7], q[8]], [q[6], q[8], q[9]]])
+    return q[0] + q[1:4] @ x + x @ A @ x
+
+
+@pytest.mark.parametrize("precision", [W.PREC_F64, W.PREC_MIXED_F64ACC])
+@pytest.mark.parametrize("source", ["none", "constant"])
+def test_exact_invariants_hold_from_1e4_to_1e7_walks(precision, source):
+    """Two cases whose expectation is exact at any time step under the
+    overshoot exit (section 2.3 with the martingale of the discrete walk):
+    harmonic data without a source, and constant density rho0 with the
+    quadratic data (2/3) pi G rho0 |x|^2 + h.  No step-size bias exists here,
+    so the agreement must hold at every walk count, down to the 1e7-walk
+    standard error -- a check of sqrt(dt), the trapezoid weight, 2 pi G and
+    the sign of the source term at full scale."""
+    q = _HARMONIC.copy()
+    kw = dict(box_lo=np.full(3, -1.0), box_hi=np.full(3, 1.0), stations=_ST, dt=4e-2, seed=21, G=1.0,
+              bc_kind=W.BC_QUADRATIC, precision=precision)
+    if source == "constant":
+        G, rho0 = 0.7, 1.5
+        k = 2.0 / 3.0 * np.pi * G * rho0
+        q[4] += k
+        q[7] += k
+        q[9] += k
+        kw.update(G=G, prisms=np.array([[-10, -10, -10, 10, 10, 10, rho0]], dtype=float))
+    pr = W.Problem(paths_per_station=10, bc_data=q, **kw)
+    target = np.array([_quad(q, x) for x in _ST])
+    say("case exact invariant, source", source, "precision", precision)
+    for N in DECADES:
+        st = _solve(pr.replace(paths_per_station=N), 0)
+        z = (st["mean"] - target) / st["se"]
+        say("  N", N, "z", np.round(z, 2), "rel se", np.round(st["se"] / np.abs(target), 6))
+        assert np.all(np.abs(z) < 4.0), (N, z)
