@@ -454,8 +454,13 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="bat
                                         "ops_per_step": algorithmic_ops_per_step("mixed"),
                                         "kernel_avg_ms": float(np.mean(mwalk_ms))},
                            "separate_value": msteps * K / sel,
+                           "station_estimates_per_s": {
+                               "u_rel_se_1e-3": station_estimates_per_s(
+                                   [dict(zip(mu.dtype.names, r)) for r in mu.tolist()], mval, 1e-3),
+                               "gz_rel_se_1e-2": station_estimates_per_s(
+                                   [dict(zip(mg.dtype.names, r)) for r in mg.tolist()], mval, 1e-2)},
                            "max_abs_diff_vs_f64_in_combined_se": {"u": du, "g_z": dg},
-                           # over the 64 stations; about 1 when the two estimators agree
+                           # over the 64 stations (about 1 for independent estimates)
                            "rms_diff_vs_f64_in_combined_se": {"u": float(np.sqrt(np.mean(zu * zu))),
                                                               "g_z": float(np.sqrt(np.mean(zg * zg)))}}
 
