@@ -231,12 +231,18 @@ __device__ __forceinline__ void sincos_2pi_t(double u, const BmTables& T, double
 // FP64 stream: one block -> two 53-bit uniforms in (0, 1] -> one Box-Muller
 // pair (cosine branch first): z0 = R cos(2 pi U2), z1 = R sin(2 pi U2),
 // R = sqrt(-2 ln U1).
+// ((hi << 21 | lo >> 11) + 1) * 2^-53, formed without a 64-bit integer: both
+// terms below are exact doubles and so is their sum (a 53-bit integer times
+// 2^-53), so the one rounding of the fma changes nothing.
+__device__ __forceinline__ double uniform53(uint32_t hi, uint32_t lo)
+{
+    return fma((double)hi, 0x1p-32, (double)((lo >> 11) + 1u) * 0x1p-53);
+}
+
 __device__ __forceinline__ void normals_f64(const Block& b, const BmTables& T, double& z0, double& z1)
 {
-    const uint64_t a = ((((uint64_t)b.w1) << 21) | (uint64_t)(b.w0 >> 11)) + 1ull;
-    const uint64_t c = ((((uint64_t)b.w3) << 21) | (uint64_t)(b.w2 >> 11)) + 1ull;
-    const double u1 = (double)a * 0x1p-53;
-    const double u2 = (double)c * 0x1p-53;
+    const double u1 = uniform53(b.w1, b.w0);
+    const double u2 = uniform53(b.w3, b.w2);
     const double r = sqrt_nonneg(neg2_log_t(u1, T));
     double s, co;
     sincos_2pi_t(u2, T, s, co);

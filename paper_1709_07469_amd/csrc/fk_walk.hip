@@ -306,7 +306,7 @@ struct Prec<true> {
     __device__ static T uniform(const Block& b, int j)
     {
         const uint32_t hi = j ? b.w3 : b.w1, lo = j ? b.w2 : b.w0;
-        return (double)((((uint64_t)hi << 21) | (uint64_t)(lo >> 11)) + 1u) * 0x1p-53;
+        return uniform53(hi, lo);
     }
     __device__ static T sdt(const WalkCommon& C) { return C.sdt; }
 };
