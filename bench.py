@@ -53,8 +53,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 60.71, "box_muller_pair_f64": 83.80, "box_muller_pair_f32": 20.32,
-              "step_f64": 29.48, "step_f32_f64sum": 24.99}
+ISSUE_COST = {"philox_block": 60.85, "box_muller_pair_f64": 79.65, "box_muller_pair_f32": 20.30,
+              "step_f64": 29.49, "step_f32_f64sum": 25.03}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -62,12 +62,12 @@ ISSUE_COST = {"philox_block": 60.71, "box_muller_pair_f64": 83.80, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "9311f19ed71c72bf5ff877971b9ae366a7a1558b944d801a91eaf5e7266d93b9",
-    "fetch_scale": 1.999879129085726, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 680.4375, "write_kib": 866923.65625},
-    "f64_separate": {"fetch_kib": 688.203125, "write_kib": 439520.140625},
-    "mixed_batched": {"fetch_kib": 145.03125, "write_kib": 919146.296875},
-    "mixed_separate": {"fetch_kib": 129.265625, "write_kib": 470483.5625},
+    "sources_sha256": "4cc7f4e961b3fdc89051074873cf205bf58fe97a949d9bf0563f5e8419435a4d",
+    "fetch_scale": 1.9998774603587837, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 165.8125, "write_kib": 864643.6875},
+    "f64_separate": {"fetch_kib": 178.4375, "write_kib": 437229.171875},
+    "mixed_batched": {"fetch_kib": 146.71875, "write_kib": 919349.4375},
+    "mixed_separate": {"fetch_kib": 131.75, "write_kib": 470438.765625},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")

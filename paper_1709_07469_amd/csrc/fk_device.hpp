@@ -187,7 +187,7 @@ __device__ __forceinline__ void fill_bm_tables(BmTables& T)
 // -2 ln u for u in (0, 1] with the table: u = m 2^e, m in [sqrt(1/2),
 // sqrt(2)); c = 1 + j/128 the nearest grid point, v = 1/c rounded; then
 // ln m = -ln v + ln(1 + r) with r = m v - 1 (one rounding, |r| < 0.0056), and
-// ln(1 + r) is its series to r^8 (truncation below 1e-19 relative).  Near
+// ln(1 + r) is its series to r^7 (truncation below 2.2e-17 relative).  Near
 // u = 1 the grid point is c = v = 1 and r = m - 1 exactly.
 __device__ __forceinline__ double neg2_log_t(double u, const BmTables& T)
 {
@@ -200,8 +200,7 @@ __device__ __forceinline__ double neg2_log_t(double u, const BmTables& T)
     const int j = (int)__builtin_rint(fma(m, 128.0, -128.0)) + BmTables::kLgOff;
     const double2 g = T.lg[j];
     const double r = fma(m, g.x, -1.0);
-    double p = -0x1.0000000000000p-3;            // -1/8
-    p = fma(p, r, 0x1.2492492492492p-3);         // 1/7
+    double p = 0x1.2492492492492p-3;             // 1/7
     p = fma(p, r, -0x1.5555555555555p-3);        // -1/6
     p = fma(p, r, 0x1.999999999999ap-3);         // 1/5
     p = fma(p, r, -0x1.0000000000000p-2);        // -1/4
@@ -214,8 +213,8 @@ __device__ __forceinline__ double neg2_log_t(double u, const BmTables& T)
 
 // sin and cos of 2 pi u, u in (0, 1], with the table: k = nearest integer
 // to 256 u, t = u - k/256 (exact, |t| <= 1/512), theta = 2 pi t; sin and cos
-// of theta by their series to theta^7 and theta^8 (truncation below 1e-20),
-// rotated by the table's angle 2 pi k / 256.
+// of theta by their series to theta^7 and theta^6 (truncation below 7e-18
+// relative and 2e-20 absolute), rotated by the table's angle 2 pi k / 256.
 __device__ __forceinline__ void sincos_2pi_t(double u, const BmTables& T, double& s, double& c)
 {
     const double q = __builtin_rint(256.0 * u);
@@ -225,8 +224,7 @@ __device__ __forceinline__ void sincos_2pi_t(double u, const BmTables& T, double
     double ps = fma(-0x1.a01a01a01a01ap-13, z, 0x1.1111111111111p-7);   // -1/5040, 1/120
     ps = fma(ps, z, -0x1.5555555555555p-3);                              // -1/6
     const double st = fma(th * z, ps, th);
-    double pc = fma(0x1.a01a01a01a01ap-16, z, -0x1.6c16c16c16c17p-10);  // 1/40320, -1/720
-    pc = fma(pc, z, 0x1.5555555555555p-5);                               // 1/24
+    double pc = fma(-0x1.6c16c16c16c17p-10, z, 0x1.5555555555555p-5);  // -1/720, 1/24
     pc = fma(pc, z, -0.5);
     const double ct = fma(pc, z, 1.0);
     const double2 a = T.sc[(int)q & (BmTables::kSc - 1)];
