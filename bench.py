@@ -53,8 +53,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 60.85, "box_muller_pair_f64": 79.65, "box_muller_pair_f32": 20.30,
-              "step_f64": 29.49, "step_f32_f64sum": 25.03}
+ISSUE_COST = {"philox_block": 61.06, "box_muller_pair_f64": 79.69, "box_muller_pair_f32": 20.22,
+              "step_f64": 29.45, "step_f32_f64sum": 25.07}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -62,12 +62,12 @@ ISSUE_COST = {"philox_block": 60.85, "box_muller_pair_f64": 79.65, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "4cc7f4e961b3fdc89051074873cf205bf58fe97a949d9bf0563f5e8419435a4d",
-    "fetch_scale": 1.9998774603587837, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 165.8125, "write_kib": 864643.6875},
-    "f64_separate": {"fetch_kib": 178.4375, "write_kib": 437229.171875},
-    "mixed_batched": {"fetch_kib": 146.71875, "write_kib": 919349.4375},
-    "mixed_separate": {"fetch_kib": 131.75, "write_kib": 470438.765625},
+    "sources_sha256": "67077bda2a8319f6011cab20490cc8c0587688ad65f7f9f3e85d90a388f80b19",
+    "fetch_scale": 1.9998858040213434, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 163.625, "write_kib": 864702.59375},
+    "f64_separate": {"fetch_kib": 177.046875, "write_kib": 437968.84375},
+    "mixed_batched": {"fetch_kib": 141.9375, "write_kib": 917452.0},
+    "mixed_separate": {"fetch_kib": 899.40625, "write_kib": 474637.609375},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")

@@ -197,7 +197,7 @@ __device__ __forceinline__ double neg2_log_t(double u, const BmTables& T)
         m = 2.0 * m;
         e -= 1;
     }
-    const int j = (int)__builtin_rint(fma(m, 128.0, -128.0)) + BmTables::kLgOff;
+    const int j = (int)__builtin_rint((m - 1.0) * 128.0) + BmTables::kLgOff;   // both exact
     const double2 g = T.lg[j];
     const double r = fma(m, g.x, -1.0);
     double p = 0x1.2492492492492p-3;             // 1/7

@@ -461,7 +461,8 @@ struct Walker {
 
     // Brownian-bridge test of step m from (x0, x1, x2) to y (both inside):
     // returns the face the walk stopped at (0..5; 6 = the sphere) or -1.
-    __device__ __forceinline__ int bridge_stop(const LaneProblem<F64>& P, uint32_t m, T y0, T y1, T y2) const
+    __device__ __forceinline__ int bridge_stop(const LaneProblem<F64>& P, uint32_t m, T x0, T x1, T x2, T y0, T y1,
+                                               T y2) const
     {
         constexpr int q = Prec<F64>::kNormals;
         const Block b = philox10(0x80000000u + m / q, pctr, sctr, P.pid, P.key0, P.key1);
@@ -519,64 +520,96 @@ struct Walker {
         }
     }
 
-    // One Euler-Maruyama step, to (y0, y1, y2) = x + sqrt(dt) z (advance).
-    // Returns true when the walk ends here, with how = 0: it left the domain (a = last inside
-    // point, e = the first point outside); how = 1: it reached max_steps;
-    // how = 2 + f: the bridge test stopped it at face f (e = the step's end).
-    // g is the grid density at the step's end.
-    __device__ __forceinline__ bool step(const LaneProblem<F64>& P, const typename Prec<F64>::Src& src, T y0, T y1,
-                                         T y2, T g, T& a0, T& a1, T& a2, T& e0, T& e1, T& e2, int& how)
+    // The macro-step's Euler-Maruyama steps through the points y (advance),
+    // each with its density and exit test, up to the first that ends the
+    // walk.  Returns true when the walk ended, at step at, with how = 0: it
+    // left the domain; how = 1: it reached max_steps; how = 2 + f: the bridge
+    // test stopped it at face f.  The walk's point x and density rp move to
+    // the macro-step's last point only when the walk goes on, so a walk that
+    // ended keeps them at the macro-step's start (finish recovers the step's
+    // two ends from x and y).  g holds the grid density at each point.
+    __device__ __forceinline__ bool steps(const LaneProblem<F64>& P, const typename Prec<F64>::Src& src, const T* y,
+                                          const T* g, int& at, int& how)
     {
-        T rn = T(0);
-        if (!ADJ) {
-            rn = Prec<F64>::bodies(src, g, y0, y1, y2);
-            if (F64) {
-                S = S + (double)(rp + rn);
-            } else if (KAHAN) {
-                const float y = (float)(rp + rn) - Sc;
-                const float t = Sf + y;
-                Sc = (t - Sf) - y;
-                Sf = t;
-            } else {
-                S = S + ((double)rp + (double)rn);
+        constexpr int MACRO = Prec<F64>::kMacro;
+        bool done = false;
+        T r = rp;   // the density at the step's start
+#pragma unroll
+        for (int s = 0; s < MACRO; ++s) {
+            if (done) break;
+            const T y0 = y[3 * s], y1 = y[3 * s + 1], y2 = y[3 * s + 2];
+            T rn = T(0);
+            if (!ADJ) {
+                rn = Prec<F64>::bodies(src, g[s], y0, y1, y2);
+                if (F64) {
+                    S = S + (double)(r + rn);
+                } else if (KAHAN) {
+                    const float t0 = (float)(r + rn) - Sc;
+                    const float t = Sf + t0;
+                    Sc = (t - Sf) - t0;
+                    Sf = t;
+                } else {
+                    S = S + ((double)r + (double)rn);
+                }
             }
+            n += 1;
+            bool out;
+            T d2 = T(0);
+            if (loop_exit(LOOP) >= 1 && P.ball) {
+                d2 = dist2(y0, y1, y2, P.lo0, P.lo1, P.lo2);
+                out = d2 >= P.hi0;
+            } else {
+                out = y0 <= P.lo0 || y0 >= P.hi0 || y1 <= P.lo1 || y1 >= P.hi1 || y2 <= P.lo2 || y2 >= P.hi2;
+            }
+            int stop = -1;
+            if (loop_exit(LOOP) == 2 && P.bridge && !out) {
+                const bool deep_y = deep_inside(P, y0, y1, y2, d2);
+                if (!(deep && deep_y)) {
+                    const T p0 = s ? y[3 * s - 3] : x0, p1 = s ? y[3 * s - 2] : x1, p2 = s ? y[3 * s - 1] : x2;
+                    stop = bridge_stop(P, n - 1, p0, p1, p2, y0, y1, y2);
+                }
+                deep = deep_y;
+            }
+            if (ADJ) sc.add(Prec<F64>::voxel(src, y0, y1, y2), (out || stop >= 0) ? 1 : 2);
+            if (out || stop >= 0) {
+                how = out ? 0 : 2 + stop;
+                at = s;
+                done = true;
+            } else if ((int64_t)n == P.max_steps) {
+                how = 1;
+                at = s;
+                done = true;
+            }
+            r = rn;
         }
-        n += 1;
-        bool out;
-        T d2 = T(0);
-        if (loop_exit(LOOP) >= 1 && P.ball) {
-            d2 = dist2(y0, y1, y2, P.lo0, P.lo1, P.lo2);
-            out = d2 >= P.hi0;
-        } else {
-            out = y0 <= P.lo0 || y0 >= P.hi0 || y1 <= P.lo1 || y1 >= P.hi1 || y2 <= P.lo2 || y2 >= P.hi2;
+        if (!done) {
+            x0 = y[3 * MACRO - 3];
+            x1 = y[3 * MACRO - 2];
+            x2 = y[3 * MACRO - 1];
+            rp = r;
         }
-        int stop = -1;
-        if (loop_exit(LOOP) == 2 && P.bridge && !out) {
-            const bool deep_y = deep_inside(P, y0, y1, y2, d2);
-            if (!(deep && deep_y)) stop = bridge_stop(P, n - 1, y0, y1, y2);
-            deep = deep_y;
-        }
-        if (ADJ) sc.add(Prec<F64>::voxel(src, y0, y1, y2), (out || stop >= 0) ? 1 : 2);
-        if (out || stop >= 0) {
-            a0 = x0; a1 = x1; a2 = x2;
-            e0 = y0; e1 = y1; e2 = y2;
-            how = out ? 0 : 2 + stop;
-            return true;
-        }
-        x0 = y0;
-        x1 = y1;
-        x2 = y2;
-        rp = rn;
-        if ((int64_t)n == P.max_steps) {
-            how = 1;
-            return true;
-        }
-        return false;
+        return done;
     }
 
-    // Stores the walk's exit record (or flushes its scatter) and frees the lane.
-    __device__ __forceinline__ void finish(const LaneProblem<F64>& P, T a0, T a1, T a2, T e0, T e1, T e2, int how)
+    // Stores the walk's exit record (or flushes its scatter) and frees the
+    // lane.  y holds the macro-step's points (advance) and the walk ended at
+    // step at of them: the end point is y[at], the last point inside the one
+    // before it (x for the first step).
+    __device__ __forceinline__ void finish(const LaneProblem<F64>& P, const T* y, int at, int how)
     {
+        constexpr int MACRO = Prec<F64>::kMacro;
+        T a0 = x0, a1 = x1, a2 = x2, e0 = y[0], e1 = y[1], e2 = y[2];
+#pragma unroll
+        for (int s = 1; s < MACRO; ++s) {
+            if (at == s) {
+                a0 = y[3 * s - 3];
+                a1 = y[3 * s - 2];
+                a2 = y[3 * s - 1];
+                e0 = y[3 * s];
+                e1 = y[3 * s + 1];
+                e2 = y[3 * s + 2];
+            }
+        }
         const bool capped = how == 1;
         if (ADJ) {
             sc.flush();
@@ -816,7 +849,6 @@ __device__ __forceinline__ void walk_body(const Args& A)
                 const int n_steps = B * NPB / 3;      // a multiple of MACRO
                 bool done = false;
                 int how = 0;
-                T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
                 for (int s0 = 0; s0 < n_steps && !done; s0 += MACRO) {
                     T zz[3 * MACRO];
 #pragma unroll
@@ -824,19 +856,15 @@ __device__ __forceinline__ void walk_body(const Args& A)
                         const int q = 3 * s0 + c;
                         zz[c] = tail_z[wave][(q / NPB) * m + rank][q % NPB];
                     }
+                    int at = 0;
                     with_source([&](const typename Prec<F64>::Src& src) {
                         T g[MACRO];
                         W.advance(P, src, zz, g);
-#pragma unroll
-                        for (int s = 0; s < MACRO; ++s) {
-                            if (!done)
-                                done = W.step(P, src, zz[3 * s], zz[3 * s + 1], zz[3 * s + 2], g[s], a0, a1, a2, e0,
-                                              e1, e2, how);
-                        }
+                        done = W.steps(P, src, zz, g, at, how);
                     });
+                    if (done) W.finish(P, zz, at, how);
                 }
                 W.k += (uint32_t)B;
-                if (done) W.finish(P, a0, a1, a2, e0, e1, e2, how);
             }
             wave_sync_lds();
             continue;
@@ -853,18 +881,13 @@ __device__ __forceinline__ void walk_body(const Args& A)
         }
         W.k += 3;
         bool done = false;
-        int how = 0;
-        T a0 = T(0), a1 = T(0), a2 = T(0), e0 = T(0), e1 = T(0), e2 = T(0);
+        int how = 0, at = 0;
         with_source([&](const typename Prec<F64>::Src& src) {
             T g[MACRO];
             W.advance(P, src, z, g);
-#pragma unroll
-            for (int s = 0; s < MACRO; ++s) {
-                if (!done)
-                    done = W.step(P, src, z[3 * s], z[3 * s + 1], z[3 * s + 2], g[s], a0, a1, a2, e0, e1, e2, how);
-            }
+            done = W.steps(P, src, z, g, at, how);
         });
-        if (done) W.finish(P, a0, a1, a2, e0, e1, e2, how);
+        if (done) W.finish(P, z, at, how);
     }
     if constexpr (ADJ) {
         // every wavefront has left the loop: the table's entries go out
@@ -909,8 +932,13 @@ __device__ __forceinline__ void walk_body(const Args& A)
 #define FK_BATCH_F32_GRID_BLOCKS_PER_CU 4
 #endif
 
+// The adjoint's blocks are held to 3 per CU by their LDS (the 32 KiB table
+// and the drain buffers), so their registers are bounded for 3.
+constexpr int kAdjBlocksPerCu = 3;
+
 template <bool F64, bool KAHAN, bool ADJ, int LOOP>
-__global__ void __launch_bounds__(256, F64                ? FK_F64_BLOCKS_PER_CU
+__global__ void __launch_bounds__(256, ADJ                ? kAdjBlocksPerCu
+                                       : F64             ? FK_F64_BLOCKS_PER_CU
                                        : loop_grid(LOOP) ? FK_F32_GRID_BLOCKS_PER_CU
                                                          : FK_F32_BLOCKS_PER_CU)
     walk_kernel(const typename std::conditional<F64, WalkArgsF64, WalkArgsF32>::type A)
