@@ -53,8 +53,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 61.06, "box_muller_pair_f64": 79.69, "box_muller_pair_f32": 20.22,
-              "step_f64": 29.45, "step_f32_f64sum": 25.07}
+ISSUE_COST = {"philox_block": 60.97, "box_muller_pair_f64": 79.51, "box_muller_pair_f32": 20.23,
+              "step_f64": 29.50, "step_f32_f64sum": 24.95}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -62,7 +62,7 @@ ISSUE_COST = {"philox_block": 61.06, "box_muller_pair_f64": 79.69, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "67077bda2a8319f6011cab20490cc8c0587688ad65f7f9f3e85d90a388f80b19",
+    "sources_sha256": "d57833fd1da4e75ade18da2b1708932885d34127d4252333f2929d112d4802d8",
     "fetch_scale": 1.9998858040213434, "write_scale": 1.0,
     "f64_batched": {"fetch_kib": 163.625, "write_kib": 864702.59375},
     "f64_separate": {"fetch_kib": 177.046875, "write_kib": 437968.84375},

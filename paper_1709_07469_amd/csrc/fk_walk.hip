@@ -520,6 +520,33 @@ struct Walker {
         }
     }
 
+    // Adds one trapezoid term rho(a) + rho(b) to the walk's sum.
+    __device__ __forceinline__ void add_trapezoid(T a, T b)
+    {
+        if (F64) {
+            S = S + (double)(a + b);
+        } else if (KAHAN) {
+            const float t0 = (float)(a + b) - Sc;
+            const float t = Sf + t0;
+            Sc = (t - Sf) - t0;
+            Sf = t;
+        } else {
+            S = S + ((double)a + (double)b);
+        }
+    }
+
+    // Whether y has left the domain (on the boundary counts as left); d2 is
+    // the squared distance from the ball's centre (ball domains only).
+    __device__ __forceinline__ static bool leaves(const LaneProblem<F64>& P, T y0, T y1, T y2, T& d2)
+    {
+        if (loop_exit(LOOP) >= 1 && P.ball) {
+            d2 = dist2(y0, y1, y2, P.lo0, P.lo1, P.lo2);
+            return d2 >= P.hi0;
+        }
+        d2 = T(0);
+        return (y0 <= P.lo0) | (y0 >= P.hi0) | (y1 <= P.lo1) | (y1 >= P.hi1) | (y2 <= P.lo2) | (y2 >= P.hi2);
+    }
+
     // The macro-step's Euler-Maruyama steps through the points y (advance),
     // each with its density and exit test, up to the first that ends the
     // walk.  Returns true when the walk ended, at step at, with how = 0: it
@@ -534,53 +561,80 @@ struct Walker {
         constexpr int MACRO = Prec<F64>::kMacro;
         bool done = false;
         T r = rp;   // the density at the step's start
+        if constexpr (!ADJ && loop_exit(LOOP) < 2) {
+            // Densities and exit tests of all the points first.  When no
+            // walk of the wavefront ends in this macro-step -- nearly always
+            // for walks of hundreds of steps -- the steps run as straight-line
+            // code, without the per-step masking of walks that ended.
+            T rn[MACRO];
+            bool out[MACRO];
+            bool end = (int64_t)n + MACRO >= P.max_steps;
 #pragma unroll
-        for (int s = 0; s < MACRO; ++s) {
-            if (done) break;
-            const T y0 = y[3 * s], y1 = y[3 * s + 1], y2 = y[3 * s + 2];
-            T rn = T(0);
-            if (!ADJ) {
-                rn = Prec<F64>::bodies(src, g[s], y0, y1, y2);
-                if (F64) {
-                    S = S + (double)(r + rn);
-                } else if (KAHAN) {
-                    const float t0 = (float)(r + rn) - Sc;
-                    const float t = Sf + t0;
-                    Sc = (t - Sf) - t0;
-                    Sf = t;
-                } else {
-                    S = S + ((double)r + (double)rn);
-                }
+            for (int s = 0; s < MACRO; ++s) {
+                T d2;
+                rn[s] = Prec<F64>::bodies(src, g[s], y[3 * s], y[3 * s + 1], y[3 * s + 2]);
+                out[s] = leaves(P, y[3 * s], y[3 * s + 1], y[3 * s + 2], d2);
+                end = end | out[s];
             }
-            n += 1;
-            bool out;
-            T d2 = T(0);
-            if (loop_exit(LOOP) >= 1 && P.ball) {
-                d2 = dist2(y0, y1, y2, P.lo0, P.lo1, P.lo2);
-                out = d2 >= P.hi0;
+            if (__ballot(end) == 0ull) {
+#pragma unroll
+                for (int s = 0; s < MACRO; ++s) {
+                    add_trapezoid(r, rn[s]);
+                    r = rn[s];
+                }
+                n += MACRO;
             } else {
-                out = y0 <= P.lo0 || y0 >= P.hi0 || y1 <= P.lo1 || y1 >= P.hi1 || y2 <= P.lo2 || y2 >= P.hi2;
-            }
-            int stop = -1;
-            if (loop_exit(LOOP) == 2 && P.bridge && !out) {
-                const bool deep_y = deep_inside(P, y0, y1, y2, d2);
-                if (!(deep && deep_y)) {
-                    const T p0 = s ? y[3 * s - 3] : x0, p1 = s ? y[3 * s - 2] : x1, p2 = s ? y[3 * s - 1] : x2;
-                    stop = bridge_stop(P, n - 1, p0, p1, p2, y0, y1, y2);
+#pragma unroll
+                for (int s = 0; s < MACRO; ++s) {
+                    if (done) break;
+                    add_trapezoid(r, rn[s]);
+                    n += 1;
+                    if (out[s]) {
+                        how = 0;
+                        at = s;
+                        done = true;
+                    } else if ((int64_t)n == P.max_steps) {
+                        how = 1;
+                        at = s;
+                        done = true;
+                    }
+                    r = rn[s];
                 }
-                deep = deep_y;
             }
-            if (ADJ) sc.add(Prec<F64>::voxel(src, y0, y1, y2), (out || stop >= 0) ? 1 : 2);
-            if (out || stop >= 0) {
-                how = out ? 0 : 2 + stop;
-                at = s;
-                done = true;
-            } else if ((int64_t)n == P.max_steps) {
-                how = 1;
-                at = s;
-                done = true;
+        } else {
+#pragma unroll
+            for (int s = 0; s < MACRO; ++s) {
+                if (done) break;
+                const T y0 = y[3 * s], y1 = y[3 * s + 1], y2 = y[3 * s + 2];
+                T rn = T(0);
+                if (!ADJ) {
+                    rn = Prec<F64>::bodies(src, g[s], y0, y1, y2);
+                    add_trapezoid(r, rn);
+                }
+                n += 1;
+                T d2;
+                const bool out = leaves(P, y0, y1, y2, d2);
+                int stop = -1;
+                if (loop_exit(LOOP) == 2 && P.bridge && !out) {
+                    const bool deep_y = deep_inside(P, y0, y1, y2, d2);
+                    if (!(deep && deep_y)) {
+                        const T p0 = s ? y[3 * s - 3] : x0, p1 = s ? y[3 * s - 2] : x1, p2 = s ? y[3 * s - 1] : x2;
+                        stop = bridge_stop(P, n - 1, p0, p1, p2, y0, y1, y2);
+                    }
+                    deep = deep_y;
+                }
+                if (ADJ) sc.add(Prec<F64>::voxel(src, y0, y1, y2), (out || stop >= 0) ? 1 : 2);
+                if (out || stop >= 0) {
+                    how = out ? 0 : 2 + stop;
+                    at = s;
+                    done = true;
+                } else if ((int64_t)n == P.max_steps) {
+                    how = 1;
+                    at = s;
+                    done = true;
+                }
+                r = rn;
             }
-            r = rn;
         }
         if (!done) {
             x0 = y[3 * MACRO - 3];
