@@ -53,8 +53,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 60.97, "box_muller_pair_f64": 79.51, "box_muller_pair_f32": 20.23,
-              "step_f64": 29.50, "step_f32_f64sum": 24.95}
+ISSUE_COST = {"philox_block": 61.05, "box_muller_pair_f64": 79.84, "box_muller_pair_f32": 20.45,
+              "step_f64": 29.56, "step_f32_f64sum": 25.13}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -62,12 +62,12 @@ ISSUE_COST = {"philox_block": 60.97, "box_muller_pair_f64": 79.51, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "d57833fd1da4e75ade18da2b1708932885d34127d4252333f2929d112d4802d8",
-    "fetch_scale": 1.9998858040213434, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 163.625, "write_kib": 864702.59375},
-    "f64_separate": {"fetch_kib": 177.046875, "write_kib": 437968.84375},
-    "mixed_batched": {"fetch_kib": 141.9375, "write_kib": 917452.0},
-    "mixed_separate": {"fetch_kib": 899.40625, "write_kib": 474637.609375},
+    "sources_sha256": "e2379482b394f79d5c7c8b8961cfe1fca7a82506982f8cb391dd210710ee72a8",
+    "fetch_scale": 1.9998810362056414, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 164.75, "write_kib": 865938.8125},
+    "f64_separate": {"fetch_kib": 164.84375, "write_kib": 438351.8125},
+    "mixed_batched": {"fetch_kib": 144.875, "write_kib": 917653.234375},
+    "mixed_separate": {"fetch_kib": 5078.078125, "write_kib": 481693.046875},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")

@@ -83,24 +83,41 @@ struct Pool {
     uint64_t next, end, left;
     bool exhausted;
     uint32_t stripe, tried;
+    uint64_t rounds;    // refill calls (one per macro-step or drain round)
+    int64_t started;    // walks started after the first fill
 };
 
 template <uint32_t STRIPES>
 __device__ __forceinline__ Pool start_pool(const Queue& Q)
 {
-    return Pool{0ull, 0ull, Q.n_tasks, false, blockIdx.x % STRIPES, 0u};
+    return Pool{0ull, 0ull, Q.n_tasks, false, blockIdx.x % STRIPES, 0u, 0ull, -64};
 }
+
+// Starting walks costs the wavefront about half a macro-step however many
+// lanes take one (the set-up code runs once for all of them), while a lane
+// left idle loses its share of every macro-step.  With walks ending at a rate
+// of lambda per macro-step, waiting for k idle lanes costs (k - 1)/(128 lambda)
+// + R/k macro-steps per walk (R = 1/2 the set-up), least for the smallest k
+// with k (k + 1) >= 128 R lambda.  lambda is the wavefront's own count of
+// walks started over its macro-steps so far: long walks (rare ends) refill
+// every lane at once, short ones wait for several.
+constexpr uint64_t kRefillCost128 = 64;   // 128 R (R = 1/4 measured the same)
 
 // Refills idle lanes from the wavefront's claimed run, claiming a new run
 // from its stripe when it is empty (and moving to the next stripe when that
 // one is used up).  Returns the task of this lane if it was idle and got
-// one, else ~0.
+// one, else ~0.  Called by the whole wavefront once per macro-step.
 template <uint32_t STRIPES>
 __device__ __forceinline__ uint64_t refill(Pool& pool, const Queue& Q, bool active)
 {
+    pool.rounds += 1;
     const uint64_t idle = __ballot(!active);
     if (idle == 0) return ~0ull;
     const uint32_t n_idle = (uint32_t)__popcll(idle);
+    // an all-idle wavefront always passes: started <= 64 rounds
+    if (!pool.exhausted && pool.started > 0 &&
+        (uint64_t)n_idle * (n_idle + 1) * pool.rounds < kRefillCost128 * (uint64_t)pool.started)
+        return ~0ull;
     // each pass claims a run or uses up one stripe: STRIPES passes at most
     for (uint32_t pass = 0; pass < STRIPES && pool.next == pool.end && !pool.exhausted; ++pass) {
         const uint64_t lo = Q.n_tasks * pool.stripe / STRIPES;
@@ -125,7 +142,9 @@ __device__ __forceinline__ uint64_t refill(Pool& pool, const Queue& Q, bool acti
     const uint32_t rank = (uint32_t)__popcll(idle & __lanemask_lt());
     uint64_t mine = ~0ull;
     if (!active && rank < avail) mine = pool.next + rank;
-    pool.next += (n_idle < avail) ? n_idle : avail;
+    const uint64_t taken = (n_idle < avail) ? n_idle : avail;
+    pool.next += taken;
+    pool.started += (int64_t)taken;
     return mine;
 }
 
