@@ -62,12 +62,12 @@ ISSUE_COST = {"philox_block": 61.05, "box_muller_pair_f64": 79.84, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "e2379482b394f79d5c7c8b8961cfe1fca7a82506982f8cb391dd210710ee72a8",
-    "fetch_scale": 1.9998810362056414, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 164.75, "write_kib": 865938.8125},
-    "f64_separate": {"fetch_kib": 164.84375, "write_kib": 438351.8125},
-    "mixed_batched": {"fetch_kib": 144.875, "write_kib": 917653.234375},
-    "mixed_separate": {"fetch_kib": 5078.078125, "write_kib": 481693.046875},
+    "sources_sha256": "8f23455651ab88980754a0346b741213371d15fbb0fc71cec146952abc73ec26",
+    "fetch_scale": 1.999884135283262, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 168.5, "write_kib": 868294.375},
+    "f64_separate": {"fetch_kib": 175.15625, "write_kib": 437743.328125},
+    "mixed_batched": {"fetch_kib": 147.15625, "write_kib": 915474.953125},
+    "mixed_separate": {"fetch_kib": 4310.1875, "write_kib": 477622.546875},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")

@@ -17,7 +17,10 @@
 //   - lanes whose walk has ended are refilled at macro-step boundaries, where
 //     every active lane is at the start of a Philox block triple: FP64 walks
 //     take 2 steps (6 normals = 3 blocks), mixed walks take 4 steps
-//     (12 normals = 3 blocks) per macro-step;
+//     (12 normals = 3 blocks) per macro-step; a wavefront whose walks end
+//     often waits for several idle lanes and starts their walks together;
+//   - a macro-step in which no walk of the wavefront ends runs its steps as
+//     straight-line code;
 //   - drain rounds: once the queue is empty, all 64 lanes of a wavefront
 //     generate Philox blocks and normals for its remaining live walks into
 //     LDS (any lane can compute any walk's block, the generator being
