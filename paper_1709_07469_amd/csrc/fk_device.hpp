@@ -466,8 +466,6 @@ __device__ __forceinline__ void intersect_ball(const double* c, double r2, const
 // Dirichlet data.
 // ---------------------------------------------------------------------------
 
-// ln(a + sqrt(a^2 + s)) with s = sum of the other two squares; for a < 0 the
-// sum a + r cancels, and a + r = s / (r - a) is used instead.
 // Tables of the prism closed form, in LDS: the log grid of BmTables and
 // atan(k/64), k = 0..64 (library atan, filled at the start of the launch).
 struct AtanTable {
@@ -499,33 +497,50 @@ __device__ __forceinline__ DataTables fill_data_tables()
 // ln x for a positive finite x, from the table-driven -2 ln x.
 __device__ __forceinline__ double ln_t(double x, const BmTables& T) { return -0.5 * neg2_log_t(x, T); }
 
-// atan(n / d) for finite n and d != 0: t = min(|n|, |d|) / max(|n|, |d|) in
-// [0, 1] (one division), c = k/64 the nearest grid point and
-// atan t = atan c + atan(delta), delta = (t - c)/(1 + t c), |delta| <= 1/128,
-// by its series to delta^9 (truncation below 1e-24); pi/2 - atan t when
-// |n| > |d|, and the sign of n/d.
+// 1/q for a positive normal q: the hardware estimate and two Newton steps
+// (each squares the relative error), within about 1 ulp.
+__device__ __forceinline__ double recip(double q)
+{
+    double y = __builtin_amdgcn_rcp(q);
+    y = fma(fma(-q, y, 1.0), y, y);
+    return fma(fma(-q, y, 1.0), y, y);
+}
+
+// atan(n / d) for finite n and d != 0.  With u = min(|n|, |d|) and
+// v = max(|n|, |d|), t = u / v lies in [0, 1]; c = k/64 is a grid point near
+// t (k from the reciprocal estimate, any k with |t - c| <= 1/128 + 1e-9 does)
+// and atan t = atan c + atan(delta) with delta = (u - c v)/(v + c u), one
+// division, its series to delta^9 (truncation below 1e-24); pi/2 - atan t
+// when |n| > |d|, and the sign of n/d.  No branches.
 __device__ __forceinline__ double atan_q(double n, double d, const AtanTable& A)
 {
     const double an = fabs(n), ad = fabs(d);
     const bool swap = an > ad;
-    const double t = swap ? ad / an : an / ad;
-    const double k = __builtin_rint(t * (double)AtanTable::kN);
+    const double u = swap ? ad : an, v = swap ? an : ad;
+    double k = __builtin_rint(u * __builtin_amdgcn_rcp(v) * (double)AtanTable::kN);
+    k = fmin(fmax(k, 0.0), (double)AtanTable::kN);
     const double c = k * (1.0 / AtanTable::kN);
-    const double dl = (t - c) / fma(t, c, 1.0);
+    const double dl = fma(-c, v, u) / fma(c, u, v);
     const double z = dl * dl;
     double p = fma(z, 0x1.c71c71c71c71cp-4, -0x1.2492492492492p-3);   // 1/9, -1/7
     p = fma(p, z, 0x1.999999999999ap-3);                                // 1/5
     p = fma(p, z, -0x1.5555555555555p-2);                               // -1/3
     double a = A.at[(int)k] + fma(dl * z, p, dl);
-    if (swap) a = 0x1.921fb54442d18p+0 - a;                             // pi/2
+    a = swap ? 0x1.921fb54442d18p+0 - a : a;                            // pi/2
     return ((n < 0.0) != (d < 0.0)) ? -a : a;
 }
 
 // ln(a + r) with r = sqrt(a^2 + s), s > 0: for a < 0 the sum cancels, and
-// a + r = s / (r - a) is used instead.
+// a + r = s / (r - a) is used instead (s times the reciprocal).  The
+// callers also evaluate terms they then discard (s = 0 or a = r = 0); their
+// argument is replaced by 1 so that the table lookup stays in range.
 __device__ __forceinline__ double log_shift(double a, double r, double s, const BmTables& T)
 {
-    return ln_t(a >= 0.0 ? a + r : s / (r - a), T);
+    const bool pos = a >= 0.0;
+    const double q = pos ? a + r : r - a;
+    double x = pos ? q : s * recip(q);
+    x = (x > 0.0 && x <= 0x1.fffffffffffffp+1023) ? x : 1.0;
+    return ln_t(x, T);
 }
 
 // Newtonian integral of the unit-density prism [lo, hi] seen from p: the
@@ -533,25 +548,36 @@ __device__ __forceinline__ double log_shift(double a, double r, double s, const 
 //   XY ln(Z+r) + YZ ln(X+r) + ZX ln(Y+r)
 //   - X^2/2 atan(YZ/(Xr)) - Y^2/2 atan(ZX/(Yr)) - Z^2/2 atan(XY/(Zr))
 // with corner (X, Y, Z) = corner - p and sign + at the upper corner (Nagy,
-// Papp & Benedek 2000); a term whose prefactor is zero vanishes.
+// Papp & Benedek 2000); a term whose prefactor is zero vanishes.  Every
+// term is evaluated and the vanishing ones are selected away (their
+// logarithm or quotient may be infinite), so the lanes of a wavefront --
+// whose exit points differ -- take no branches.
 __device__ inline double prism_newton(const double* q, double px, double py, double pz, const DataTables& tb)
 {
     const BmTables& T = *tb.bm;
     const AtanTable& A = *tb.at;
     double v = 0.0;
+#pragma unroll
     for (int corner = 0; corner < 8; ++corner) {
         const double X = ((corner & 1) ? q[3] : q[0]) - px;
         const double Y = ((corner & 2) ? q[4] : q[1]) - py;
         const double Z = ((corner & 4) ? q[5] : q[2]) - pz;
         const double X2 = X * X, Y2 = Y * Y, Z2 = Z * Z;
         const double r = sqrt(X2 + Y2 + Z2);
+        const double XY = X * Y, YZ = Y * Z, ZX = Z * X;
         double f = 0.0;
-        if (X * Y != 0.0) f += X * Y * log_shift(Z, r, X2 + Y2, T);
-        if (Y * Z != 0.0) f += Y * Z * log_shift(X, r, Y2 + Z2, T);
-        if (Z * X != 0.0) f += Z * X * log_shift(Y, r, Z2 + X2, T);
-        if (X != 0.0) f -= 0.5 * X2 * atan_q(Y * Z, X * r, A);
-        if (Y != 0.0) f -= 0.5 * Y2 * atan_q(Z * X, Y * r, A);
-        if (Z != 0.0) f -= 0.5 * Z2 * atan_q(X * Y, Z * r, A);
+        const double l1 = XY * log_shift(Z, r, X2 + Y2, T);
+        f += (XY != 0.0) ? l1 : 0.0;
+        const double l2 = YZ * log_shift(X, r, Y2 + Z2, T);
+        f += (YZ != 0.0) ? l2 : 0.0;
+        const double l3 = ZX * log_shift(Y, r, Z2 + X2, T);
+        f += (ZX != 0.0) ? l3 : 0.0;
+        const double t1 = 0.5 * X2 * atan_q(YZ, X * r, A);
+        f -= (X != 0.0) ? t1 : 0.0;
+        const double t2 = 0.5 * Y2 * atan_q(ZX, Y * r, A);
+        f -= (Y != 0.0) ? t2 : 0.0;
+        const double t3 = 0.5 * Z2 * atan_q(XY, Z * r, A);
+        f -= (Z != 0.0) ? t3 : 0.0;
         // sign (-1)^(i+j+k) with index 1 = lower, 2 = upper corner: positive
         // when the number of upper coordinates is odd
         const int uppers = (corner & 1) + ((corner >> 1) & 1) + ((corner >> 2) & 1);

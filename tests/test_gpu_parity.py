@@ -120,6 +120,19 @@ def test_f64_face_grid_data(exit_rule):
     _check_f64_potential(pr)
 
 
+@pytest.mark.parametrize("exit_rule", [W.EXIT_OVERSHOOT, W.EXIT_INTERSECT])
+def test_f64_prism_data_with_prisms_on_the_boundary(exit_rule):
+    """Prisms touching box faces, their closed form as the data: under
+    INTERSECT the exit points lie on those faces, so corner offsets are exactly
+    zero and the terms with a zero prefactor vanish -- in the kernels they are
+    evaluated and selected away, with the table lookups kept in range."""
+    prisms = np.array([[0.2, -0.4, -1.0, 1.0, 0.3, -0.5, 2.0], [-1.0, -1.0, 0.4, -0.6, 1.0, 1.0, -1.2]])
+    pr = W.Problem(stations=_ST4, dt=1e-2, paths_per_station=1500, seed=13, G=1.0, bc_kind=W.BC_PRISMS,
+                   bc_data=prisms.ravel().copy(), prisms=prisms, exit_rule=exit_rule,
+                   name=f"boundary-prisms-exit{exit_rule}", **_BOX)
+    _check_f64_potential(pr)
+
+
 def test_f64_truncation_parity():
     pr = W.cfg1(1500).replace(max_steps=150)
     st, ost = _check_f64_potential(pr)
