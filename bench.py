@@ -53,8 +53,8 @@ PEAK_LANE_OPS = 256 * 64 * 2.4e9
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 60.59, "box_muller_pair_f64": 79.06, "box_muller_pair_f32": 20.23,
-              "step_f64": 29.44, "step_f32_f64sum": 24.92}
+ISSUE_COST = {"philox_block": 60.80, "box_muller_pair_f64": 79.69, "box_muller_pair_f32": 20.20,
+              "step_f64": 29.36, "step_f32_f64sum": 24.92}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -62,12 +62,12 @@ ISSUE_COST = {"philox_block": 60.59, "box_muller_pair_f64": 79.06, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "3bfedf811a25d545a5c9f6a38e158d7aa28715599a7d748aa80da28a42f80b47",
-    "fetch_scale": 1.9998796058653638, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 168.5625, "write_kib": 868061.25},
-    "f64_separate": {"fetch_kib": 175.546875, "write_kib": 437840.2265625},
-    "mixed_batched": {"fetch_kib": 147.34375, "write_kib": 915280.765625},
-    "mixed_separate": {"fetch_kib": 4244.328125, "write_kib": 477548.1796875},
+    "sources_sha256": "549d2c53215d6e32db3e1c6de9246798ae7d23eee9ce27bc4cbe12246359cbcb",
+    "fetch_scale": 1.9998815129861887, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 162.625, "write_kib": 868206.21875},
+    "f64_separate": {"fetch_kib": 175.1875, "write_kib": 437846.2421875},
+    "mixed_batched": {"fetch_kib": 150.125, "write_kib": 915371.03125},
+    "mixed_separate": {"fetch_kib": 4238.96875, "write_kib": 477679.34375},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")

@@ -215,40 +215,48 @@ __device__ __forceinline__ bool forward_capped(const WalkCommon& C, uint64_t t)
 // face on most steps of a fine grid, and every global atomic on device memory
 // is performed at the memory side (hundreds of cycles, limited in flight), so
 // the walks of a block -- which start from the same stations and crowd the
-// same voxels -- first add into the table.  Each slot is one 64-bit word,
-// (index + 1) << 32 | int32 count, updated by compare-and-swap only, so it is
-// atomic across the block's wavefronts; a different index evicts the slot's
-// entry to the global counts, and counts that would leave +-2^30 go there
-// directly.  The table is flushed when the block's walks are done.  Integer
-// sums in any order: the counts are exact and the same as without the table.
-#ifndef FK_ADJ_TABLE_BITS
-#define FK_ADJ_TABLE_BITS 12
-#endif
-constexpr int kAdjTableBits = FK_ADJ_TABLE_BITS;
-constexpr int kAdjSlots = 1 << kAdjTableBits;   // 12 bits: 32 KiB of LDS per block
+// same voxels -- first add into the table.  Each slot is one 32-bit word,
+// (index + 1) << 11 | 11-bit signed count, updated by compare-and-swap only,
+// so it is atomic across the block's wavefronts; a different index evicts the
+// slot's entry to the global counts, a count that would leave +-1024 goes
+// there as well, and so does every weight whose index + 1 needs more than 21
+// bits or whose size is 1024 or more.  The table is flushed when the block's
+// walks are done.  Integer sums in any order: the counts are exact and the
+// same as without the table.
+constexpr int kAdjTableBits = 13;
+constexpr int kAdjSlots = 1 << kAdjTableBits;    // 32 KiB of LDS per block
+constexpr int kAdjCountBits = 11;
+constexpr uint32_t kAdjKeyLimit = 1u << (32 - kAdjCountBits);
+constexpr int64_t kAdjBound = 1ll << (kAdjCountBits - 1);
 
 __device__ __forceinline__ void global_add(int64_t* counts, int64_t idx, int64_t w)
 {
     atomicAdd(reinterpret_cast<unsigned long long*>(counts + idx), (unsigned long long)w);
 }
 
-__device__ __forceinline__ void adj_emit(unsigned long long* tab, int64_t* counts, int64_t idx, int64_t w)
+// The key (index + 1, 0 = empty) and the signed count of a table word.
+__device__ __forceinline__ uint32_t adj_key(uint32_t e) { return e >> kAdjCountBits; }
+__device__ __forceinline__ int64_t adj_count(uint32_t e)
 {
-    constexpr int64_t kBound = 1ll << 30;
-    if ((uint64_t)idx >= 0xFFFFFFFEull || w >= kBound || w <= -kBound) {
+    return (int64_t)((int32_t)(e << (32 - kAdjCountBits)) >> (32 - kAdjCountBits));
+}
+
+__device__ __forceinline__ void adj_emit(uint32_t* tab, int64_t* counts, int64_t idx, int64_t w)
+{
+    if ((uint64_t)idx + 1 >= kAdjKeyLimit || w >= kAdjBound || w <= -kAdjBound) {
         global_add(counts, idx, w);
         return;
     }
     const uint32_t k1 = (uint32_t)idx + 1u;
     const uint32_t slot = ((uint32_t)idx * 2654435761u) >> (32 - kAdjTableBits);
-    unsigned long long cur = __hip_atomic_load(&tab[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    uint32_t cur = __hip_atomic_load(&tab[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     for (;;) {
-        const uint32_t ck = (uint32_t)(cur >> 32);
-        const int64_t cc = (int32_t)(uint32_t)cur;
+        const uint32_t ck = adj_key(cur);
+        const int64_t cc = adj_count(cur);
         int64_t keep = w, out_idx = -1, out_c = 0;   // out: what leaves the table if this swap wins
         if (ck == k1) {
             keep = cc + w;
-            if (keep >= kBound || keep <= -kBound) {
+            if (keep >= kAdjBound || keep <= -kAdjBound) {
                 out_idx = idx;
                 out_c = keep;
                 keep = 0;
@@ -257,8 +265,8 @@ __device__ __forceinline__ void adj_emit(unsigned long long* tab, int64_t* count
             out_idx = (int64_t)ck - 1;
             out_c = cc;
         }
-        const unsigned long long want = ((unsigned long long)k1 << 32) | (uint32_t)(int32_t)keep;
-        const unsigned long long prev = atomicCAS(&tab[slot], cur, want);
+        const uint32_t want = (k1 << kAdjCountBits) | ((uint32_t)keep & ((1u << kAdjCountBits) - 1u));
+        const uint32_t prev = atomicCAS(&tab[slot], cur, want);
         if (prev == cur) {
             if (out_c != 0) global_add(counts, out_idx, out_c);
             return;
@@ -270,7 +278,7 @@ __device__ __forceinline__ void adj_emit(unsigned long long* tab, int64_t* count
 // Run-length coalesced scatter of one walk's signed trapezoid weights.
 struct Scatter {
     int64_t* counts;            // the problem's counts
-    unsigned long long* tab;    // the block's table
+    uint32_t* tab;              // the block's table
     int64_t row;                // station offset into counts
     int64_t v;                  // pending voxel (-1: none)
     int64_t c;                  // pending weight
@@ -810,11 +818,11 @@ __device__ __forceinline__ void walk_body(const Args& A)
     W.n = W.k = W.sctr = W.pctr = 0;
     W.deep = false;
     W.sc = Scatter{nullptr, nullptr, 0, -1, 0, 1};
-    unsigned long long* adj_tab = nullptr;
+    uint32_t* adj_tab = nullptr;
     if constexpr (ADJ) {
         static_assert(!BATCH, "the adjoint runs single-problem launches");
-        __shared__ unsigned long long tab[kAdjSlots];
-        for (int i = threadIdx.x; i < kAdjSlots; i += blockDim.x) tab[i] = 0ull;
+        __shared__ uint32_t tab[kAdjSlots];
+        for (int i = threadIdx.x; i < kAdjSlots; i += blockDim.x) tab[i] = 0u;
         __syncthreads();
         adj_tab = tab;
     }
@@ -969,9 +977,9 @@ __device__ __forceinline__ void walk_body(const Args& A)
         // every wavefront has left the loop: the table's entries go out
         __syncthreads();
         for (int i = threadIdx.x; i < kAdjSlots; i += blockDim.x) {
-            const unsigned long long e = adj_tab[i];
-            const int64_t c = (int32_t)(uint32_t)e;
-            if ((e >> 32) != 0 && c != 0) global_add(A.c.counts, (int64_t)(e >> 32) - 1, c);
+            const uint32_t e = adj_tab[i];
+            const int64_t c = adj_count(e);
+            if (adj_key(e) != 0 && c != 0) global_add(A.c.counts, (int64_t)adj_key(e) - 1, c);
         }
     }
 }

@@ -33,10 +33,35 @@ def _counts_from_workspace(aws, S, nvox):
 
 @pytest.mark.parametrize("kind", [0, 1])
 def test_adjoint_counts_equal_oracle_occupation(kind):
+    pr = W.cfg5(300)
+    _check_counts(pr.replace(stations=pr.stations[::6]), kind)
+
+
+def _coarse_grid(n, dt, paths, n_stations):
+    """Zero data, an n^3 grid of random densities over [-1, 1]^3."""
+    rng = np.random.Generator(np.random.PCG64(n))
+    st = np.stack([rng.uniform(-0.6, 0.6, n_stations), rng.uniform(-0.6, 0.6, n_stations),
+                   rng.uniform(-0.6, 0.6, n_stations)], axis=1)
+    o = np.full(3, -1.0)
+    return W.Problem(box_lo=o.copy(), box_hi=-o, stations=st, dt=dt, paths_per_station=paths, seed=3,
+                     rho=rng.uniform(0.5, 2.0, size=(n, n, n)), grid_origin=o, grid_spacing=np.full(3, 2.0 / n),
+                     name=f"grid{n}")
+
+
+@pytest.mark.parametrize("case", ["long-runs", "wide-index"])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_adjoint_counts_at_the_table_limits(kind, case):
+    """The LDS table holds 11-bit counts under 21-bit keys and passes the rest
+    to the global counts: a 2^3 grid at dt = 1e-4 gives runs of hundreds of
+    steps in one voxel (weights past the count range) and slots that overflow;
+    a 64^3 grid with 9 stations puts station x voxel indices past 2^21."""
+    pr = _coarse_grid(2, 1e-4, 60, 2) if case == "long-runs" else _coarse_grid(64, 1e-3, 24, 9)
+    _check_counts(pr, kind)
+
+
+def _check_counts(pr, kind):
     import torch
     from paper_1709_07469_amd import fkgrav as F
-    pr = W.cfg5(300)
-    pr = pr.replace(stations=pr.stations[::6])
     S = pr.n_stations
     nvox = pr.rho.size
     rng = np.random.Generator(np.random.PCG64(1))
