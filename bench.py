@@ -43,6 +43,10 @@ METRIC = "Brownian steps/s and station estimates/s at fixed std error; % FP32/FP
 # lane-operations per second (the same count that gives 78.6 TFLOP/s of FP64
 # FMA at 2 FLOP per lane-op).  One "lane-slot" is one such operation.
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# MI355X's published vector peaks: FP64 78.6 TFLOP/s; FP32 157.3 TFLOP/s
+# (packed FP32, which these kernels do not use; 78.6 without it).
+PEAK_F64_FLOPS = 78.6e12
+PEAK_F32_FLOPS = 157.3e12
 
 # Issue cost, in lane-slots, of the parts one Euler-Maruyama step is made of,
 # each measured alone on MI355X by paper_1709_07469_amd/fk_issue_probe (eight
@@ -68,6 +72,19 @@ PMC_BYTES = {
     "f64_separate": {"fetch_kib": 175.1875, "write_kib": 437846.2421875},
     "mixed_batched": {"fetch_kib": 150.125, "write_kib": 915371.03125},
     "mixed_separate": {"fetch_kib": 4238.96875, "write_kib": 477679.34375},
+}
+# VALU counters of the walk kernels per Brownian step (rocprofv3 --pmc
+# SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, GRBM_GUI_ACTIVE and the
+# SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F{64,32} counts, FLOP = ADD + MUL + 2 FMA +
+# TRANS, each times 64 lanes), recorded like PMC_BYTES for the sources hashed
+# in "sources_sha256"; with the measured steps/s they give the fractions of
+# the FP64 and FP32 vector peaks.
+VALU_COUNTERS = {
+    "sources_sha256": "549d2c53215d6e32db3e1c6de9246798ae7d23eee9ce27bc4cbe12246359cbcb",
+    "f64_batched": {"valu_lane_instr_per_step": 250.3, "valu_busy": 0.9648, "fp64_flop_per_step": 108.16, "fp32_flop_per_step": 0.07},
+    "f64_separate": {"valu_lane_instr_per_step": 251.6, "valu_busy": 0.9267, "fp64_flop_per_step": 109.14, "fp32_flop_per_step": 0.13},
+    "mixed_batched": {"valu_lane_instr_per_step": 105.7, "valu_busy": 1.048, "fp64_flop_per_step": 2.2, "fp32_flop_per_step": 20.56},
+    "mixed_separate": {"valu_lane_instr_per_step": 105.2, "valu_busy": 0.9717, "fp64_flop_per_step": 2.49, "fp32_flop_per_step": 21.57},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")
@@ -101,6 +118,22 @@ def measured_traffic(precision: str, mode: str):
         return None
     r = PMC_BYTES[key]
     return r["fetch_kib"] * 1024 * PMC_BYTES["fetch_scale"] + r["write_kib"] * 1024 * PMC_BYTES["write_scale"]
+
+
+def valu_counters(precision: str, mode: str, kernel_steps_per_s: float):
+    """The walk kernel's counters per Brownian step and the FLOP rates they
+    give at the kernel's measured steps/s, or None when they were taken on
+    other kernel sources or another launch form."""
+    key = precision + "_" + mode
+    if not VALU_COUNTERS or VALU_COUNTERS.get("sources_sha256") != sources_sha256() or key not in VALU_COUNTERS:
+        return None
+    c = VALU_COUNTERS[key]
+    f64 = c["fp64_flop_per_step"] * kernel_steps_per_s
+    f32 = c["fp32_flop_per_step"] * kernel_steps_per_s
+    return {"valu_busy": c["valu_busy"], "valu_lane_instr_per_step": c["valu_lane_instr_per_step"],
+            "fp64_flop_per_step": c["fp64_flop_per_step"], "fp32_flop_per_step": c["fp32_flop_per_step"],
+            "fp64_tflops": f64 / 1e12, "fp64_frac_of_peak": f64 / PEAK_F64_FLOPS,
+            "fp32_tflops": f32 / 1e12, "fp32_frac_of_peak": f32 / PEAK_F32_FLOPS}
 
 
 def station_estimates_per_s(stats, steps_per_s, rel_se):
@@ -403,7 +436,8 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="bat
             "kernel_avg_ms": float(np.mean(walk_ms)), "launches": len(walk_ms),
             "kernel_share_of_step": sum(walk_ms) / (elapsed * 1e3),
             "algorithmic_bytes_per_launch": algo_bytes,
-            "traffic_over_algorithmic": None if traffic is None else traffic / algo_bytes}
+            "traffic_over_algorithmic": None if traffic is None else traffic / algo_bytes,
+            "counters": valu_counters(precision_name, mode, steps_per_pass * K / (sum(walk_ms) * 1e-3))}
 
     rows_u = [dict(zip(su.dtype.names, r)) for r in su.tolist()]
     rows_g = [dict(zip(sg.dtype.names, r)) for r in sg.tolist()]
@@ -452,7 +486,9 @@ def run(precision_name, K, Wm, cpu_seconds, want_cpu, want_paper=True, mode="bat
                                         "frac": mach / peak, "traffic": measured_traffic("mixed", "batched"),
                                         "kernel": "batch_walk_kernel<F32, F64 sum>",
                                         "ops_per_step": algorithmic_ops_per_step("mixed"),
-                                        "kernel_avg_ms": float(np.mean(mwalk_ms))},
+                                        "kernel_avg_ms": float(np.mean(mwalk_ms)),
+                                        "counters": valu_counters("mixed", "batched",
+                                                                  msteps * K / (sum(mwalk_ms) * 1e-3))},
                            "separate_value": msteps * K / sel,
                            "station_estimates_per_s": {
                                "u_rel_se_1e-3": station_estimates_per_s(
