@@ -57,8 +57,8 @@ PEAK_F32_FLOPS = 157.3e12
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 60.80, "box_muller_pair_f64": 79.69, "box_muller_pair_f32": 20.20,
-              "step_f64": 29.36, "step_f32_f64sum": 24.92}
+ISSUE_COST = {"philox_block": 60.76, "box_muller_pair_f64": 79.34, "box_muller_pair_f32": 20.23,
+              "step_f64": 29.52, "step_f32_f64sum": 25.07}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -66,12 +66,12 @@ ISSUE_COST = {"philox_block": 60.80, "box_muller_pair_f64": 79.69, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "549d2c53215d6e32db3e1c6de9246798ae7d23eee9ce27bc4cbe12246359cbcb",
-    "fetch_scale": 1.9998815129861887, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 162.625, "write_kib": 868206.21875},
-    "f64_separate": {"fetch_kib": 175.1875, "write_kib": 437846.2421875},
-    "mixed_batched": {"fetch_kib": 150.125, "write_kib": 915371.03125},
-    "mixed_separate": {"fetch_kib": 4238.96875, "write_kib": 477679.34375},
+    "sources_sha256": "146cc58903b467c79b1b4c16319bcb8680cf4764309cee58ccc7e5501e855fc0",
+    "fetch_scale": 1.999883181719894, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 167.125, "write_kib": 868127.0},
+    "f64_separate": {"fetch_kib": 188.46875, "write_kib": 437390.140625},
+    "mixed_batched": {"fetch_kib": 150.09375, "write_kib": 914840.296875},
+    "mixed_separate": {"fetch_kib": 14558.203125, "write_kib": 491583.9375},
 }
 # VALU counters of the walk kernels per Brownian step (rocprofv3 --pmc
 # SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, GRBM_GUI_ACTIVE and the
@@ -80,11 +80,11 @@ PMC_BYTES = {
 # in "sources_sha256"; with the measured steps/s they give the fractions of
 # the FP64 and FP32 vector peaks.
 VALU_COUNTERS = {
-    "sources_sha256": "549d2c53215d6e32db3e1c6de9246798ae7d23eee9ce27bc4cbe12246359cbcb",
-    "f64_batched": {"valu_lane_instr_per_step": 250.3, "valu_busy": 0.9648, "fp64_flop_per_step": 108.16, "fp32_flop_per_step": 0.07},
-    "f64_separate": {"valu_lane_instr_per_step": 251.6, "valu_busy": 0.9267, "fp64_flop_per_step": 109.14, "fp32_flop_per_step": 0.13},
-    "mixed_batched": {"valu_lane_instr_per_step": 105.7, "valu_busy": 1.048, "fp64_flop_per_step": 2.2, "fp32_flop_per_step": 20.56},
-    "mixed_separate": {"valu_lane_instr_per_step": 105.2, "valu_busy": 0.9717, "fp64_flop_per_step": 2.49, "fp32_flop_per_step": 21.57},
+    "sources_sha256": "146cc58903b467c79b1b4c16319bcb8680cf4764309cee58ccc7e5501e855fc0",
+    "f64_batched": {"valu_lane_instr_per_step": 250.3, "valu_busy": 0.9724, "fp64_flop_per_step": 108.16, "fp32_flop_per_step": 0.07},
+    "f64_separate": {"valu_lane_instr_per_step": 249.9, "valu_busy": 0.9447, "fp64_flop_per_step": 109.14, "fp32_flop_per_step": 0.13},
+    "mixed_batched": {"valu_lane_instr_per_step": 105.7, "valu_busy": 1.0888, "fp64_flop_per_step": 2.2, "fp32_flop_per_step": 20.55},
+    "mixed_separate": {"valu_lane_instr_per_step": 105.4, "valu_busy": 1.0351, "fp64_flop_per_step": 2.49, "fp32_flop_per_step": 21.55},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")

@@ -295,9 +295,9 @@ __device__ __forceinline__ int64_t voxel_f64(const SourceF64& s, double x, doubl
 // The membership tests are combined without short-circuiting and the sum is
 // selected, not branched on: a body's bounds then load together (one wait
 // instead of one per bound) and no lane diverges.
-__device__ __forceinline__ double bodies_f64(const SourceF64& s, double r, double x, double y, double z)
+__device__ __forceinline__ double bodies_f64(const SourceF64& s, double r, double x, double y, double z, int j0 = 0)
 {
-    for (int j = 0; j < s.n_prisms; ++j) {
+    for (int j = j0; j < s.n_prisms; ++j) {
         const double* q = s.prisms[j];
         const bool in = (x >= q[0]) & (x < q[3]) & (y >= q[1]) & (y < q[4]) & (z >= q[2]) & (z < q[5]);
         r = in ? r + q[6] : r;
@@ -353,9 +353,9 @@ __device__ __forceinline__ int voxel_f32(const SourceF32& s, float x, float y, f
     return in ? ((int)tz * s.n[1] + (int)ty) * s.n[0] + (int)tx : -1;
 }
 
-__device__ __forceinline__ float bodies_f32(const SourceF32& s, float r, float x, float y, float z)
+__device__ __forceinline__ float bodies_f32(const SourceF32& s, float r, float x, float y, float z, int j0 = 0)
 {
-    for (int j = 0; j < s.n_prisms; ++j) {
+    for (int j = j0; j < s.n_prisms; ++j) {
         const float* q = s.prisms[j];
         const bool in = (x >= q[0]) & (x < q[3]) & (y >= q[1]) & (y < q[4]) & (z >= q[2]) & (z < q[5]);
         r = in ? r + q[6] : r;

@@ -323,7 +323,7 @@ struct Prec<true> {
     __device__ static T fmat(T a, T b, T c) { return fma(a, b, c); }
     __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f64(s, x, y, z); }
     __device__ static T grid_in(const Src& s, T x, T y, T z) { return grid_in_f64(s, x, y, z); }
-    __device__ static T bodies(const Src& s, T g, T x, T y, T z) { return bodies_f64(s, g, x, y, z); }
+    __device__ static T bodies(const Src& s, T g, T x, T y, T z, int j0 = 0) { return bodies_f64(s, g, x, y, z, j0); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f64(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo[c]; }
     __device__ static T hi(const WalkCommon& C, int c) { return C.hi[c]; }
@@ -355,7 +355,7 @@ struct Prec<false> {
     __device__ static T fmat(T a, T b, T c) { return fmaf(a, b, c); }
     __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f32(s, x, y, z); }
     __device__ static T grid_in(const Src& s, T x, T y, T z) { return grid_in_f32(s, x, y, z); }
-    __device__ static T bodies(const Src& s, T g, T x, T y, T z) { return bodies_f32(s, g, x, y, z); }
+    __device__ static T bodies(const Src& s, T g, T x, T y, T z, int j0 = 0) { return bodies_f32(s, g, x, y, z, j0); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f32(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo_f[c]; }
     __device__ static T hi(const WalkCommon& C, int c) { return C.hi_f[c]; }
@@ -585,8 +585,23 @@ struct Walker {
     // the macro-step's last point only when the walk goes on, so a walk that
     // ended keeps them at the macro-step's start (finish recovers the step's
     // two ends from x and y).  g holds the grid density at each point.
+    // The source's density at y: the grid value g, then the analytic bodies
+    // in their order.  With HELD the first prism comes from hq (registers;
+    // lo = +inf when the source has none) and the rest from the source.
+    template <bool HELD>
+    __device__ __forceinline__ static T density(const typename Prec<F64>::Src& src, const T* hq, T g, T y0, T y1, T y2)
+    {
+        if constexpr (HELD) {
+            const bool in = (y0 >= hq[0]) & (y0 < hq[3]) & (y1 >= hq[1]) & (y1 < hq[4]) & (y2 >= hq[2]) & (y2 < hq[5]);
+            return Prec<F64>::bodies(src, in ? g + hq[6] : g, y0, y1, y2, 1);
+        } else {
+            return Prec<F64>::bodies(src, g, y0, y1, y2);
+        }
+    }
+
+    template <bool HELD = false>
     __device__ __forceinline__ bool steps(const LaneProblem<F64>& P, const typename Prec<F64>::Src& src, const T* y,
-                                          const T* g, int& at, int& how)
+                                          const T* g, int& at, int& how, const T* hq = nullptr)
     {
         constexpr int MACRO = Prec<F64>::kMacro;
         bool done = false;
@@ -602,7 +617,7 @@ struct Walker {
 #pragma unroll
             for (int s = 0; s < MACRO; ++s) {
                 T d2;
-                rn[s] = Prec<F64>::bodies(src, g[s], y[3 * s], y[3 * s + 1], y[3 * s + 2]);
+                rn[s] = density<HELD>(src, hq, g[s], y[3 * s], y[3 * s + 1], y[3 * s + 2]);
                 out[s] = leaves(P, y[3 * s], y[3 * s + 1], y[3 * s + 2], d2);
                 end = end | out[s];
             }
@@ -638,7 +653,7 @@ struct Walker {
                 const T y0 = y[3 * s], y1 = y[3 * s + 1], y2 = y[3 * s + 2];
                 T rn = T(0);
                 if (!ADJ) {
-                    rn = Prec<F64>::bodies(src, g[s], y0, y1, y2);
+                    rn = density<HELD>(src, hq, g[s], y0, y1, y2);
                     add_trapezoid(r, rn);
                 }
                 n += 1;
@@ -808,6 +823,10 @@ __device__ __forceinline__ void walk_body(const Args& A)
         }
     };
     constexpr uint32_t STRIPES = (BATCH && !SHARED) ? kStripes : 1u;
+    // drain rounds hold the first prism in registers (below); not in grid
+    // loops, whose sources are mostly grids, nor in FP64 batches, whose
+    // registers it costs more than it gains (both measured)
+    constexpr bool kHeld = !loop_grid(LOOP) && !(F64 && BATCH);
     Pool pool = start_pool<STRIPES>(Q);
     Walker<F64, KAHAN, ADJ, LOOP> W;
     W.active = false;
@@ -933,20 +952,47 @@ __device__ __forceinline__ void walk_body(const Args& A)
                 const int n_steps = B * NPB / 3;      // a multiple of MACRO
                 bool done = false;
                 int how = 0;
-                for (int s0 = 0; s0 < n_steps && !done; s0 += MACRO) {
-                    T zz[3 * MACRO];
-#pragma unroll
-                    for (int c = 0; c < 3 * MACRO; ++c) {
-                        const int q = 3 * s0 + c;
-                        zz[c] = tail_z[wave][(q / NPB) * m + rank][q % NPB];
-                    }
-                    int at = 0;
+                if constexpr (kHeld) {
+                    // A walk stepping alone here has no other wavefronts to
+                    // hide the latency of re-reading the source's bodies at
+                    // every step: the first prism is held in registers for
+                    // the round.
                     with_source([&](const typename Prec<F64>::Src& src) {
-                        T g[MACRO];
-                        W.advance(P, src, zz, g);
-                        done = W.steps(P, src, zz, g, at, how);
+                        const bool any = src.n_prisms > 0;
+                        T hq[7];
+#pragma unroll
+                        for (int c = 0; c < 7; ++c)
+                            hq[c] = in_vgpr(any ? (T)src.prisms[0][c] : (c == 0 ? (T)__builtin_inf() : T(0)));
+                        for (int s0 = 0; s0 < n_steps && !done; s0 += MACRO) {
+                            T zz[3 * MACRO];
+#pragma unroll
+                            for (int c = 0; c < 3 * MACRO; ++c) {
+                                const int q = 3 * s0 + c;
+                                zz[c] = tail_z[wave][(q / NPB) * m + rank][q % NPB];
+                            }
+                            int at = 0;
+                            T g[MACRO];
+                            W.advance(P, src, zz, g);
+                            done = W.template steps<true>(P, src, zz, g, at, how, hq);
+                            if (done) W.finish(P, zz, at, how);
+                        }
                     });
-                    if (done) W.finish(P, zz, at, how);
+                } else {
+                    for (int s0 = 0; s0 < n_steps && !done; s0 += MACRO) {
+                        T zz[3 * MACRO];
+#pragma unroll
+                        for (int c = 0; c < 3 * MACRO; ++c) {
+                            const int q = 3 * s0 + c;
+                            zz[c] = tail_z[wave][(q / NPB) * m + rank][q % NPB];
+                        }
+                        int at = 0;
+                        with_source([&](const typename Prec<F64>::Src& src) {
+                            T g[MACRO];
+                            W.advance(P, src, zz, g);
+                            done = W.steps(P, src, zz, g, at, how);
+                        });
+                        if (done) W.finish(P, zz, at, how);
+                    }
                 }
                 W.k += (uint32_t)B;
             }
