@@ -57,8 +57,8 @@ PEAK_F32_FLOPS = 157.3e12
 #   step_*                position update, density of one analytic prism,
 #                         trapezoid sum and exit test (FP64; FP32 with an
 #                         FP64 sum)
-ISSUE_COST = {"philox_block": 60.76, "box_muller_pair_f64": 79.34, "box_muller_pair_f32": 20.23,
-              "step_f64": 29.52, "step_f32_f64sum": 25.07}
+ISSUE_COST = {"philox_block": 60.82, "box_muller_pair_f64": 79.46, "box_muller_pair_f32": 20.31,
+              "step_f64": 29.54, "step_f32_f64sum": 25.01}
 
 # HBM bytes of the walk kernels on this workload, from two rocprofv3 --pmc
 # runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged
@@ -66,12 +66,12 @@ ISSUE_COST = {"philox_block": 60.76, "box_muller_pair_f64": 79.34, "box_muller_p
 # a 1 GiB device-to-device copy.  They describe the kernel sources hashed in
 # "sources_sha256" only; for any other source the traffic is reported as null.
 PMC_BYTES = {
-    "sources_sha256": "146cc58903b467c79b1b4c16319bcb8680cf4764309cee58ccc7e5501e855fc0",
-    "fetch_scale": 1.999883181719894, "write_scale": 1.0,
-    "f64_batched": {"fetch_kib": 167.125, "write_kib": 868127.0},
-    "f64_separate": {"fetch_kib": 188.46875, "write_kib": 437390.140625},
-    "mixed_batched": {"fetch_kib": 150.09375, "write_kib": 914840.296875},
-    "mixed_separate": {"fetch_kib": 14558.203125, "write_kib": 491583.9375},
+    "sources_sha256": "7e95cd34b6c3e8ae15958d54f1bd9b4bda9fb76400ceb974b20135f0f609960d",
+    "fetch_scale": 1.9998796058653638, "write_scale": 1.0,
+    "f64_batched": {"fetch_kib": 153.75, "write_kib": 868267.125},
+    "f64_separate": {"fetch_kib": 1894.25, "write_kib": 444061.8828125},
+    "mixed_batched": {"fetch_kib": 151.84375, "write_kib": 914944.671875},
+    "mixed_separate": {"fetch_kib": 14555.109375, "write_kib": 491642.7890625},
 }
 # VALU counters of the walk kernels per Brownian step (rocprofv3 --pmc
 # SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, GRBM_GUI_ACTIVE and the
@@ -80,11 +80,11 @@ PMC_BYTES = {
 # in "sources_sha256"; with the measured steps/s they give the fractions of
 # the FP64 and FP32 vector peaks.
 VALU_COUNTERS = {
-    "sources_sha256": "146cc58903b467c79b1b4c16319bcb8680cf4764309cee58ccc7e5501e855fc0",
-    "f64_batched": {"valu_lane_instr_per_step": 250.3, "valu_busy": 0.9724, "fp64_flop_per_step": 108.16, "fp32_flop_per_step": 0.07},
-    "f64_separate": {"valu_lane_instr_per_step": 249.9, "valu_busy": 0.9447, "fp64_flop_per_step": 109.14, "fp32_flop_per_step": 0.13},
-    "mixed_batched": {"valu_lane_instr_per_step": 105.7, "valu_busy": 1.0888, "fp64_flop_per_step": 2.2, "fp32_flop_per_step": 20.55},
-    "mixed_separate": {"valu_lane_instr_per_step": 105.4, "valu_busy": 1.0351, "fp64_flop_per_step": 2.49, "fp32_flop_per_step": 21.55},
+    "sources_sha256": "7e95cd34b6c3e8ae15958d54f1bd9b4bda9fb76400ceb974b20135f0f609960d",
+    "f64_batched": {"valu_lane_instr_per_step": 250.3, "valu_busy": 0.968, "fp64_flop_per_step": 108.15, "fp32_flop_per_step": 0.07},
+    "f64_separate": {"valu_lane_instr_per_step": 252.2, "valu_busy": 0.9492, "fp64_flop_per_step": 109.15, "fp32_flop_per_step": 0.13},
+    "mixed_batched": {"valu_lane_instr_per_step": 105.7, "valu_busy": 1.0852, "fp64_flop_per_step": 2.2, "fp32_flop_per_step": 20.55},
+    "mixed_separate": {"valu_lane_instr_per_step": 105.3, "valu_busy": 1.0382, "fp64_flop_per_step": 2.5, "fp32_flop_per_step": 21.56},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp")

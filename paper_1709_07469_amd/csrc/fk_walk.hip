@@ -526,10 +526,10 @@ struct Walker {
     // reach (as if none ended the walk) and, with a grid, loads the grid
     // density at each, all loads issued before the first is used.  Points past
     // the walk's end are never used.
+    template <int MACRO = Prec<F64>::kMacro>
     __device__ __forceinline__ void advance(const LaneProblem<F64>& P, const typename Prec<F64>::Src& src, T* z,
                                             T* g) const
     {
-        constexpr int MACRO = Prec<F64>::kMacro;
         T p0 = x0, p1 = x1, p2 = x2;
 #pragma unroll
         for (int s = 0; s < MACRO; ++s) {
@@ -599,11 +599,10 @@ struct Walker {
         }
     }
 
-    template <bool HELD = false>
+    template <bool HELD = false, int MACRO = Prec<F64>::kMacro>
     __device__ __forceinline__ bool steps(const LaneProblem<F64>& P, const typename Prec<F64>::Src& src, const T* y,
                                           const T* g, int& at, int& how, const T* hq = nullptr)
     {
-        constexpr int MACRO = Prec<F64>::kMacro;
         bool done = false;
         T r = rp;   // the density at the step's start
         if constexpr (!ADJ && loop_exit(LOOP) < 2) {
@@ -694,9 +693,9 @@ struct Walker {
     // lane.  y holds the macro-step's points (advance) and the walk ended at
     // step at of them: the end point is y[at], the last point inside the one
     // before it (x for the first step).
+    template <int MACRO = Prec<F64>::kMacro>
     __device__ __forceinline__ void finish(const LaneProblem<F64>& P, const T* y, int at, int how)
     {
-        constexpr int MACRO = Prec<F64>::kMacro;
         T a0 = x0, a1 = x1, a2 = x2, e0 = y[0], e1 = y[1], e2 = y[2];
 #pragma unroll
         for (int s = 1; s < MACRO; ++s) {
@@ -963,18 +962,38 @@ __device__ __forceinline__ void walk_body(const Args& A)
 #pragma unroll
                         for (int c = 0; c < 7; ++c)
                             hq[c] = in_vgpr(any ? (T)src.prisms[0][c] : (c == 0 ? (T)__builtin_inf() : T(0)));
-                        for (int s0 = 0; s0 < n_steps && !done; s0 += MACRO) {
-                            T zz[3 * MACRO];
+                        // FP64: two macro-steps at a time while the round has
+                        // them, so that their densities and exit tests overlap
+                        // (mixed walks measured slower so: registers)
+                        constexpr int DRAIN = F64 ? 2 * MACRO : MACRO;
+                        int s0 = 0;
+                        for (; s0 + DRAIN <= n_steps && !done; s0 += DRAIN) {
+                            T zz[3 * DRAIN];
 #pragma unroll
-                            for (int c = 0; c < 3 * MACRO; ++c) {
+                            for (int c = 0; c < 3 * DRAIN; ++c) {
                                 const int q = 3 * s0 + c;
                                 zz[c] = tail_z[wave][(q / NPB) * m + rank][q % NPB];
                             }
                             int at = 0;
-                            T g[MACRO];
-                            W.advance(P, src, zz, g);
-                            done = W.template steps<true>(P, src, zz, g, at, how, hq);
-                            if (done) W.finish(P, zz, at, how);
+                            T g[DRAIN];
+                            W.template advance<DRAIN>(P, src, zz, g);
+                            done = W.template steps<true, DRAIN>(P, src, zz, g, at, how, hq);
+                            if (done) W.template finish<DRAIN>(P, zz, at, how);
+                        }
+                        if constexpr (DRAIN != MACRO) {
+                            for (; s0 < n_steps && !done; s0 += MACRO) {
+                                T zz[3 * MACRO];
+#pragma unroll
+                                for (int c = 0; c < 3 * MACRO; ++c) {
+                                    const int q = 3 * s0 + c;
+                                    zz[c] = tail_z[wave][(q / NPB) * m + rank][q % NPB];
+                                }
+                                int at = 0;
+                                T g[MACRO];
+                                W.advance(P, src, zz, g);
+                                done = W.template steps<true>(P, src, zz, g, at, how, hq);
+                                if (done) W.finish(P, zz, at, how);
+                            }
                         }
                     });
                 } else {
