@@ -36,6 +36,10 @@
  *     the null stream).  Device inputs must stay valid until the stream has
  *     passed the call.  The library keeps no pointer after it returns and
  *     allocates no device memory: scratch comes from the caller's workspace.
+ *   - A solve's workspace begins with a 256-byte status block whose first
+ *     word collects the FK_FLAG_* anomaly bits of the solve's walks (set on
+ *     the device, read by fk_workspace_status without a synchronisation
+ *     inside the solve).
  *   - All argument checks run on the host before any launch.  On an error
  *     nothing is launched, outputs are untouched and fk_last_error() holds a
  *     message.  No C++ exception crosses this interface.
@@ -59,9 +63,20 @@ typedef enum {
     FK_EDOMAIN = -2,       /* a station (or station +- h e_z) is not strictly inside the box */
     FK_EWORKSPACE = -3,    /* workspace smaller than fk_workspace_bytes() or misaligned */
     FK_EDEVICE = -4,       /* a HIP runtime call failed */
-    FK_ETRUNC = -5,        /* reserved: strict mode reports truncated walks through fk_stat */
-    FK_EUNSUPPORTED = -6   /* a size limit of the library is exceeded (see FK_MAX_*) */
+    FK_ETRUNC = -5,        /* fk_workspace_status: a strict solve capped walks at max_steps */
+    FK_EUNSUPPORTED = -6,  /* a size limit of the library is exceeded (see FK_MAX_*) */
+    FK_ENONFINITE = -7     /* fk_workspace_status: a walk sample was NaN or infinite */
 } fk_status;
+
+/* Anomaly bits of a solve's status word (fk_workspace_status).  The
+ * reduction ORs them in on the device as it forms the walk samples. */
+typedef enum {
+    FK_FLAG_TRUNCATED = 1,  /* a walk hit max_steps, or started on or outside the boundary; it is
+                             * excluded from mean and variance and counted in fk_stat.n_trunc */
+    FK_FLAG_NONFINITE = 2,  /* an uncapped walk's sample is NaN or infinite (a NaN or infinite density,
+                             * position or boundary datum); it enters mean and variance as it is */
+    FK_FLAG_STRICT = 256    /* the solve ran with fk_params.strict set */
+} fk_flag;
 
 typedef enum {
     FK_F64 = 0,            /* FP64 stream, FP64 stepping and accumulation */
@@ -162,11 +177,18 @@ typedef struct {
     int32_t precision;           /* fk_precision */
     int32_t exit_rule;           /* fk_exit_rule */
     int32_t pairing;             /* fk_pairing (g_z only) */
-    int32_t strict;              /* nonzero: FK_ETRUNC-style reporting via fk_stat.n_trunc only (reserved) */
+    int32_t strict;              /* nonzero: fk_workspace_status reports capped walks as FK_ETRUNC */
     int64_t max_steps;           /* cap per walk, 1 .. 2^31-1; capped walks are excluded and counted */
     uint32_t problem_id;         /* counter word m */
     int32_t domain;              /* fk_domain */
     int64_t path_offset;         /* first path index p */
+    int64_t slice_walks;         /* 0: the workspace keeps every walk's record (the per-walk samples stay
+                                  * inspectable, fk_workspace_layout).  > 0: bounded workspace -- the walks
+                                  * run in slices of at most this many (at least 8192 per walk of a pair,
+                                  * i.e. 8192 for a potential, 16384 for g_z), each slice a run of whole
+                                  * (station, 8192-path chunk) pairs reduced before the next starts, so the
+                                  * workspace holds one slice's records and every pair's partial
+                                  * statistics; results are bit for bit those of record mode */
 } fk_params;
 
 /* Per-station result.  For fk_solve_gz the samples are the pair differences
@@ -196,17 +218,27 @@ typedef struct {
 } fk_problem;
 
 /* Bytes of device workspace a solve needs (host, pure).  kind 0 = potential,
- * 1 = g_z.  The workspace begins with the per-path samples of the last solve,
- * laid out as described by fk_workspace_layout. */
+ * 1 = g_z.  With params->slice_walks = 0 the workspace holds every walk's
+ * record (about 44 bytes per walk) and keeps the per-path samples of the last
+ * solve, laid out as described by fk_workspace_layout; with slice_walks > 0 it
+ * holds 36 bytes per walk of one slice plus 48 bytes per (station, chunk)
+ * pair, whatever the walk count.  0 for invalid parameters. */
 size_t fk_workspace_bytes(int32_t kind, int64_t n_stations, const fk_params *params);
 
 /* Offsets (bytes from the workspace start) of the per-path arrays a solve
  * leaves behind: values (double) and steps (uint32, bit 31 set for a walk that
  * hit max_steps).  Potential: index s*N + i.  g_z: index (s*N + i)*2 + w with
  * w = 0 for the walk from x0 + h e_z and 1 for x0 - h e_z.  Values of capped
- * walks are NaN. */
+ * walks are NaN.  Record mode only (slice_walks = 0; else FK_EINVAL). */
 fk_status fk_workspace_layout(int32_t kind, int64_t n_stations, const fk_params *params,
                               size_t *values_offset, size_t *steps_offset, size_t *total_bytes);
+
+/* Anomaly report of the last solve (single or batched) run in a workspace:
+ * waits for hip_stream, copies the status word to *flags (HOST, nullable;
+ * FK_FLAG_* bits) and returns FK_ENONFINITE if some sample was not finite,
+ * else FK_ETRUNC if the solve was strict and capped some walk, else FK_OK.
+ * workspace: DEVICE, the solve's workspace (its first 256 bytes). */
+fk_status fk_workspace_status(const void *workspace, uint32_t *flags, void *hip_stream);
 
 /* Host-side check that every station (HOST, n_stations x 3) lies strictly
  * inside the box -- for kind 1 also x0 +- h e_z.  Returns FK_EDOMAIN naming the
@@ -244,7 +276,10 @@ fk_status fk_solve_gz(const double *stations, int64_t n_stations, const fk_box *
 size_t fk_batch_workspace_bytes(const fk_problem *problems, int32_t n_problems);
 
 /* Offsets (bytes from the workspace start) of problem m's per-walk values and
- * step counts after fk_solve_batch, laid out as in fk_workspace_layout. */
+ * step counts after fk_solve_batch, laid out as in fk_workspace_layout.
+ * Record mode only.  A batch's slice_walks (the same for every problem) works
+ * as for a single solve: slices are runs of whole (station, chunk) pairs of
+ * the problems in order. */
 fk_status fk_batch_layout(const fk_problem *problems, int32_t n_problems, int32_t m, size_t *values_offset,
                           size_t *steps_offset);
 
@@ -264,7 +299,8 @@ fk_status fk_solve_batch(const fk_problem *problems, int32_t n_problems, fk_stat
  * in a fixed order, so the result is deterministic.  The boundary data is held
  * fixed (it does not depend on rho).
  *   forward_out, forward_workspace: DEVICE results and workspace of the forward
- *     solve with the same arguments (walks capped there are skipped here);
+ *     solve with the same arguments, run in record mode (slice_walks = 0;
+ *     walks capped there are skipped here);
  *   grad_out: DEVICE, n_stations doubles; grad_rho: DEVICE, one double per
  *     voxel, overwritten; workspace: DEVICE, fk_adjoint_workspace_bytes().
  * The source must have a voxel grid. */

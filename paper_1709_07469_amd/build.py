@@ -11,7 +11,6 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfkgrav.so")
-PROBE = os.path.join(PKG, "fk_issue_probe")
 SOURCES = ["fk_walk.hip", "fk_reduce.hip", "fk_batch.hip", "fk_api.cpp"]
 ARCH = os.environ.get("FKGRAV_ARCH", "gfx950")
 
@@ -49,13 +48,6 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
-    # the issue-cost probe behind the walk kernels' ALU roofline
-    tmp = PROBE + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *HIPFLAGS, "-x", "hip", os.path.join(CSRC, "fk_issue_probe.hip"), "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, PROBE)
     return LIB
 
 

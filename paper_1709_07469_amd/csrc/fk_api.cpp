@@ -101,11 +101,25 @@ void timing_end(const std::pair<hipEvent_t, hipEvent_t>& ev, hipStream_t stream)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Workspace of a single solve (256-byte aligned regions):
+//   status    the status word (FK_FLAG_* bits) in a 256-byte block
+//   values    per-walk samples, record mode only (8 B per task)
+//   steps     step counts of the records held at once (4 B each)
+//   exits     exit records of the records held at once (32 B each)
+//   partials  one Partial per (station, chunk) pair
+//   queue     the claim counters
+// Record mode holds every task's record; a bounded workspace holds the
+// records of one slice (at most slice_walks tasks).
 struct Layout {
     int64_t n_tasks;
     int64_t n_chunks;
-    size_t values, steps, exits, partials, queue, total;
+    int64_t n_pairs;
+    int64_t held;            // records held at once
+    bool records;            // record mode
+    size_t status, values, steps, exits, partials, queue, total;
 };
+
+constexpr size_t kStatusBytes = 256;
 
 bool is_finite(double v) { return std::isfinite(v); }
 
@@ -133,21 +147,97 @@ fk_status check_params(int32_t kind, int64_t n_stations, const fk_params* p)
     if (kind == 1 && p->pairing == FK_PAIR_INDEPENDENT && n_stations > (1ll << 31))
         return fail(FK_EUNSUPPORTED, "independent pairing needs 2 * n_stations < 2^32");
     if (n_stations > (1ll << 32)) return fail(FK_EUNSUPPORTED, "n_stations must be < 2^32");
+    if (p->slice_walks < 0) return fail(FK_EINVAL, "slice_walks must be >= 0");
+    if (p->slice_walks > 0 && p->slice_walks < kChunk * npair)
+        return fail(FK_EINVAL, "slice_walks must be 0 or at least %lld (8192 per walk of a pair)",
+                    (long long)(kChunk * npair));
+    const int64_t n_chunks = (p->paths_per_station + kChunk - 1) / kChunk;
+    if (n_stations > 0 && n_chunks > ((1ll << 31) - 1) / n_stations)
+        return fail(FK_EUNSUPPORTED, "n_stations * ceil(paths_per_station / 8192) must be < 2^31");
     return FK_OK;
 }
 
-Layout make_layout(int32_t kind, int64_t n_stations, const fk_params* p)
+// slice_walks: 0 = record mode, else the bound on the records held at once.
+Layout make_layout(int32_t kind, int64_t n_stations, const fk_params* p, int64_t slice_walks)
 {
     Layout L{};
     L.n_tasks = n_stations * p->paths_per_station * (kind == 1 ? 2 : 1);
     L.n_chunks = (p->paths_per_station + kChunk - 1) / kChunk;
-    L.values = 0;
-    L.steps = align256(L.values + sizeof(double) * (size_t)L.n_tasks);
-    L.exits = align256(L.steps + sizeof(uint32_t) * (size_t)L.n_tasks);
-    L.partials = align256(L.exits + sizeof(fk::ExitRecord) * (size_t)L.n_tasks);
-    L.queue = align256(L.partials + sizeof(fk::Partial) * (size_t)(n_stations * L.n_chunks));
+    L.n_pairs = n_stations * L.n_chunks;
+    L.records = slice_walks == 0;
+    L.held = L.records ? L.n_tasks : std::min(L.n_tasks, slice_walks);
+    L.status = 0;
+    L.values = kStatusBytes;
+    L.steps = align256(L.values + (L.records ? sizeof(double) * (size_t)L.n_tasks : 0));
+    L.exits = align256(L.steps + sizeof(uint32_t) * (size_t)L.held);
+    L.partials = align256(L.exits + sizeof(fk::ExitRecord) * (size_t)L.held);
+    L.queue = align256(L.partials + sizeof(fk::Partial) * (size_t)L.n_pairs);
     L.total = align256(L.queue + 256);
     return L;
+}
+
+Layout make_layout(int32_t kind, int64_t n_stations, const fk_params* p)
+{
+    return make_layout(kind, n_stations, p, p->slice_walks);
+}
+
+// A slice: the tasks [t0, t1) and the (station, chunk) pairs [q0, q1) they
+// make up, numbered across the problems of a solve in order.
+struct Slice {
+    int64_t t0, t1, q0, q1;
+};
+
+// One problem's shape: stations, walks per station and pair, chunks per
+// station.
+struct Shape {
+    int64_t S, N, npair, n_chunks;
+};
+
+// Cuts the tasks of the problems into slices of at most `budget` tasks
+// (budget >= kChunk * npair of every problem), each a run of whole
+// (station, chunk) pairs, and calls fn(slice) on each in order until fn
+// returns an error.  Stations that fit go into a slice whole, as many as fit;
+// a station larger than the budget is cut into runs of chunks.
+template <class F>
+fk_status for_each_slice(const std::vector<Shape>& shapes, int64_t budget, F&& fn)
+{
+    Slice cur{0, 0, 0, 0};
+    fk_status st = FK_OK;
+    auto close = [&]() {
+        if (cur.t1 > cur.t0 && st == FK_OK) st = fn(cur);
+        cur = Slice{cur.t1, cur.t1, cur.q1, cur.q1};
+    };
+    for (const Shape& p : shapes) {
+        if (p.S == 0) continue;
+        const int64_t per_station = p.N * p.npair;
+        if (per_station <= budget) {
+            int64_t s = 0;
+            while (s < p.S && st == FK_OK) {
+                const int64_t k = std::min(p.S - s, (budget - (cur.t1 - cur.t0)) / per_station);
+                if (k == 0) {
+                    close();
+                    continue;
+                }
+                cur.t1 += k * per_station;
+                cur.q1 += k * p.n_chunks;
+                s += k;
+            }
+        } else {
+            close();
+            const int64_t run = budget / (kChunk * p.npair);
+            for (int64_t s = 0; s < p.S && st == FK_OK; ++s)
+                for (int64_t c0 = 0; c0 < p.n_chunks && st == FK_OK; c0 += run) {
+                    const int64_t c1 = std::min(p.n_chunks, c0 + run);
+                    const int64_t i1 = std::min(p.N, c1 * kChunk);
+                    cur.t1 = cur.t0 + (i1 - c0 * kChunk) * p.npair;
+                    cur.q1 = cur.q0 + (c1 - c0);
+                    close();
+                }
+        }
+        if (st != FK_OK) return st;
+    }
+    close();
+    return st;
 }
 
 fk_status check_box(const fk_box* b)
@@ -265,6 +355,7 @@ void fill_common(fk::WalkCommon& C, int32_t kind, const double* stations, int64_
     C.n_stations = n_stations;
     C.N = p->paths_per_station;
     C.n_tasks = L.n_tasks;
+    C.task0 = 0;
     C.path_offset = p->path_offset;
     C.max_steps = p->max_steps;
     for (int c = 0; c < 3; ++c) {
@@ -409,9 +500,9 @@ fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool b
     return FK_OK;
 }
 
-fk_status solve(int32_t kind, const double* stations, int64_t n_stations, const fk_box* box, const fk_source* src,
-                const fk_boundary* bc, const fk_params* p, fk_stat* out, void* workspace, size_t workspace_bytes,
-                void* hip_stream)
+// Checks every argument of a single solve except the workspace.
+fk_status check_solve(int32_t kind, const double* stations, int64_t n_stations, const fk_box* box,
+                      const fk_source* src, const fk_boundary* bc, const fk_params* p, const fk_stat* out)
 {
     fk_status st;
     if ((st = check_params(kind, n_stations, p)) != FK_OK) return st;
@@ -422,51 +513,32 @@ fk_status solve(int32_t kind, const double* stations, int64_t n_stations, const 
     if (n_stations == 0) return FK_OK;
     if (!stations) return fail(FK_EINVAL, "stations is NULL");
     if (!out) return fail(FK_EINVAL, "out is NULL");
-    const Layout L = make_layout(kind, n_stations, p);
-    if (!workspace) return fail(FK_EINVAL, "workspace is NULL");
-    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FK_EWORKSPACE, "workspace must be 256-byte aligned");
-    if (workspace_bytes < L.total)
-        return fail(FK_EWORKSPACE, "workspace has %zu bytes, %zu needed", workspace_bytes, L.total);
-    if (kind == 1) {
-        const double h = p->h > 0.0 ? p->h : std::sqrt(p->dt);
-        if (!(h > 0.0)) return fail(FK_EINVAL, "difference step h must be > 0");
-    }
-    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-    char* ws = static_cast<char*>(workspace);
+    return FK_OK;
+}
 
-    fk::LaunchCfg cfg;
-    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p, src))) != FK_OK) return st;
-
+// Enqueues a checked single solve in the workspace ws laid out as L: the
+// status word set, then per slice the walks and the partials of its pairs,
+// then the station results.  timing: the walk launches may be event-timed.
+fk_status run_solve(int32_t kind, const double* stations, int64_t n_stations, const fk_box* box, const fk_source* src,
+                    const fk_boundary* bc, const fk_params* p, fk_stat* out, char* ws, const Layout& L,
+                    hipStream_t stream, bool timing)
+{
     fk::WalkCommon C;
     fill_common(C, kind, stations, n_stations, box, p, L, ws);
-    C.grab = cfg.grab;
-    C.total_waves = (uint32_t)((int64_t)cfg.grid * cfg.block / 64);
-
-    hipError_t e = fk::launch_zero_queue(C.queue, stream);
-    if (e != hipSuccess) return fail(FK_EDEVICE, "queue reset launch failed: %s", hipGetErrorString(e));
-    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    const bool timed = timing_begin(&ev, stream);
-    if (p->precision == FK_F64) {
-        fk::WalkArgsF64 A;
-        A.c = C;
-        fill_source_f64(A.src, src);
-        e = fk::launch_walk_f64(A, cfg, stream);
-    } else {
-        fk::WalkArgsF32 A;
-        A.c = C;
-        fill_source_f32(A.src, src);
-        e = fk::launch_walk_f32(A, p->precision == FK_MIXED_KAHAN, cfg, stream);
-    }
-    if (timed) timing_end(ev, stream);
-    if (e != hipSuccess) return fail(FK_EDEVICE, "walk launch failed: %s", hipGetErrorString(e));
+    fk::WalkArgsF64 A64;
+    fk::WalkArgsF32 A32;
+    if (p->precision == FK_F64) fill_source_f64(A64.src, src);
+    else fill_source_f32(A32.src, src);
+    uint32_t* status = reinterpret_cast<uint32_t*>(ws + L.status);
 
     fk::ReduceArgs R;
     std::memset(&R, 0, sizeof R);
     R.exits = C.exits;
-    R.values = reinterpret_cast<double*>(ws + L.values);
+    R.values = L.records ? reinterpret_cast<double*>(ws + L.values) : nullptr;
     R.steps = C.steps;
     R.partials = reinterpret_cast<fk::Partial*>(ws + L.partials);
     R.out = out;
+    R.status = status;
     R.n_stations = n_stations;
     R.N = p->paths_per_station;
     R.chunk = kChunk;
@@ -480,19 +552,74 @@ fk_status solve(int32_t kind, const double* stations, int64_t n_stations, const 
         R.hi[c] = C.hi[c];
     }
     fill_bc(R.bc, bc);
-    e = fk::launch_reduce(R, stream);
+
+    const int loop = loop_kind(p, src);
+    bool first = true;
+    const std::vector<Shape> shapes{Shape{n_stations, p->paths_per_station, C.npair, L.n_chunks}};
+    fk_status st = for_each_slice(shapes, L.held, [&](const Slice& sl) -> fk_status {
+        hipError_t e = first ? fk::launch_zero_queue(C.queue, stream, status, p->strict ? FK_FLAG_STRICT : 0u)
+                             : fk::launch_zero_queue(C.queue, stream);
+        first = false;
+        if (e != hipSuccess) return fail(FK_EDEVICE, "queue reset launch failed: %s", hipGetErrorString(e));
+        fk::LaunchCfg cfg;
+        fk_status ps = plan_launch(p->precision, sl.t1 - sl.t0, &cfg, false, loop);
+        if (ps != FK_OK) return ps;
+        C.task0 = sl.t0;
+        C.n_tasks = sl.t1 - sl.t0;
+        C.grab = cfg.grab;
+        C.total_waves = (uint32_t)((int64_t)cfg.grid * cfg.block / 64);
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        const bool timed = timing && timing_begin(&ev, stream);
+        if (p->precision == FK_F64) {
+            A64.c = C;
+            e = fk::launch_walk_f64(A64, cfg, stream);
+        } else {
+            A32.c = C;
+            e = fk::launch_walk_f32(A32, p->precision == FK_MIXED_KAHAN, cfg, stream);
+        }
+        if (timed) timing_end(ev, stream);
+        if (e != hipSuccess) return fail(FK_EDEVICE, "walk launch failed: %s", hipGetErrorString(e));
+        R.q0 = sl.q0;
+        R.task0 = sl.t0;
+        e = fk::launch_reduce(R, sl.q1 - sl.q0, false, stream);
+        if (e != hipSuccess) return fail(FK_EDEVICE, "reduction launch failed: %s", hipGetErrorString(e));
+        return FK_OK;
+    });
+    if (st != FK_OK) return st;
+    const hipError_t e = fk::launch_reduce(R, 0, true, stream);
     if (e != hipSuccess) return fail(FK_EDEVICE, "reduction launch failed: %s", hipGetErrorString(e));
     return FK_OK;
+}
+
+fk_status solve(int32_t kind, const double* stations, int64_t n_stations, const fk_box* box, const fk_source* src,
+                const fk_boundary* bc, const fk_params* p, fk_stat* out, void* workspace, size_t workspace_bytes,
+                void* hip_stream)
+{
+    fk_status st = check_solve(kind, stations, n_stations, box, src, bc, p, out);
+    if (st != FK_OK || n_stations == 0) return st;
+    const Layout L = make_layout(kind, n_stations, p);
+    if (!workspace) return fail(FK_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(FK_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (workspace_bytes < L.total)
+        return fail(FK_EWORKSPACE, "workspace has %zu bytes, %zu needed", workspace_bytes, L.total);
+    return run_solve(kind, stations, n_stations, box, src, bc, p, out, static_cast<char*>(workspace), L,
+                     reinterpret_cast<hipStream_t>(hip_stream), true);
 }
 
 // ---------------------------------------------------------------------------
 // Batched solves.
 // ---------------------------------------------------------------------------
+// Workspace of a batched solve: the status block, the problem descriptors,
+// the task and pair prefix sums, one Partial per global pair, the per-walk
+// samples by global task (record mode), the records held at once (all tasks,
+// or one slice), and the claim counters.
 struct BatchLayout {
-    size_t desc, task_off, block_off, queue, total;
-    std::vector<Layout> per;       // per-problem layouts relative to base[m]
-    std::vector<size_t> base;
-    int64_t n_tasks = 0, n_blocks = 0, n_stations = 0;
+    size_t status, desc, task_off, block_off, partials, values, steps, exits, queue, total;
+    std::vector<Shape> shapes;
+    std::vector<int64_t> tasks;    // prefix sums of tasks over the problems
+    std::vector<int64_t> pairs;    // prefix sums of (station, chunk) pairs
+    int64_t n_tasks = 0, n_pairs = 0, n_stations = 0, held = 0;
+    bool records = true;
 };
 
 static_assert(sizeof(fk::BatchDesc) % 8 == 0, "descriptor must be whole 64-bit words");
@@ -502,6 +629,7 @@ fk_status check_batch(const fk_problem* probs, int32_t n)
     if (n < 0 || n > FK_MAX_BATCH) return fail(FK_EUNSUPPORTED, "n_problems must lie in [0, %d]", FK_MAX_BATCH);
     if (n > 0 && !probs) return fail(FK_EINVAL, "problems is NULL");
     fk_status st;
+    int64_t pairs = 0;
     for (int32_t m = 0; m < n; ++m) {
         const fk_problem& P = probs[m];
         if ((st = check_params(P.kind, P.n_stations, &P.params)) != FK_OK) return st;
@@ -513,6 +641,10 @@ fk_status check_batch(const fk_problem* probs, int32_t n)
         if (P.out_offset < 0) return fail(FK_EINVAL, "problem %d: out_offset < 0", m);
         if (P.params.precision != probs[0].params.precision)
             return fail(FK_EINVAL, "problem %d: all problems of a batch need the same precision", m);
+        if (P.params.slice_walks != probs[0].params.slice_walks)
+            return fail(FK_EINVAL, "problem %d: all problems of a batch need the same slice_walks", m);
+        pairs += P.n_stations * ((P.params.paths_per_station + kChunk - 1) / kChunk);
+        if (pairs > (1ll << 31) - 1) return fail(FK_EUNSUPPORTED, "a batch must have fewer than 2^31 (station, chunk) pairs");
     }
     return FK_OK;
 }
@@ -520,21 +652,32 @@ fk_status check_batch(const fk_problem* probs, int32_t n)
 BatchLayout make_batch_layout(const fk_problem* probs, int32_t n)
 {
     BatchLayout B;
-    B.desc = 0;
+    B.tasks.assign(1, 0);
+    B.pairs.assign(1, 0);
+    for (int32_t m = 0; m < n; ++m) {
+        const fk_problem& P = probs[m];
+        const int64_t npair = P.kind == 1 ? 2 : 1;
+        const int64_t nch = (P.params.paths_per_station + kChunk - 1) / kChunk;
+        B.shapes.push_back(Shape{P.n_stations, P.params.paths_per_station, npair, nch});
+        B.n_tasks += P.n_stations * P.params.paths_per_station * npair;
+        B.n_pairs += P.n_stations * nch;
+        B.n_stations += P.n_stations;
+        B.tasks.push_back(B.n_tasks);
+        B.pairs.push_back(B.n_pairs);
+    }
+    const int64_t sw = n > 0 ? probs[0].params.slice_walks : 0;
+    B.records = sw == 0;
+    B.held = B.records ? B.n_tasks : std::min(B.n_tasks, sw);
+    B.status = 0;
+    B.desc = kStatusBytes;
     B.task_off = align256(B.desc + sizeof(fk::BatchDesc) * (size_t)n);
     B.block_off = align256(B.task_off + sizeof(int64_t) * (size_t)(n + 1));
-    size_t at = align256(B.block_off + sizeof(int64_t) * (size_t)(n + 1));
-    for (int32_t m = 0; m < n; ++m) {
-        const Layout L = make_layout(probs[m].kind, probs[m].n_stations, &probs[m].params);
-        B.per.push_back(L);
-        B.base.push_back(at);
-        at = align256(at + L.queue);       // the per-problem queue slot is not used in a batch
-        B.n_tasks += L.n_tasks;
-        B.n_blocks += probs[m].n_stations * L.n_chunks;
-        B.n_stations += probs[m].n_stations;
-    }
-    B.queue = at;
-    B.total = align256(at + 256);
+    B.partials = align256(B.block_off + sizeof(int64_t) * (size_t)(n + 1));
+    B.values = align256(B.partials + sizeof(fk::Partial) * (size_t)B.n_pairs);
+    B.steps = align256(B.values + (B.records ? sizeof(double) * (size_t)B.n_tasks : 0));
+    B.exits = align256(B.steps + sizeof(uint32_t) * (size_t)B.held);
+    B.queue = align256(B.exits + sizeof(fk::ExitRecord) * (size_t)B.held);
+    B.total = align256(B.queue + 256);
     return B;
 }
 
@@ -554,9 +697,12 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
     char* ws = static_cast<char*>(workspace);
     const int precision = probs[0].params.precision;
 
-    fk::LaunchCfg cfg;
     int loop = 0;
-    for (int32_t m = 0; m < n; ++m) loop = merge_loops(loop, loop_kind(&probs[m].params, &probs[m].source));
+    bool strict = false;
+    for (int32_t m = 0; m < n; ++m) {
+        loop = merge_loops(loop, loop_kind(&probs[m].params, &probs[m].source));
+        strict = strict || probs[m].params.strict;
+    }
     // one source for the whole batch (e.g. u and g_z of one model): the walk
     // kernel then reads it from its arguments instead of per-lane descriptors
     fk::BatchArgs A;
@@ -577,62 +723,77 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
             shared = std::memcmp(&o, &A.src32, sizeof o) == 0;
         }
     }
-    if ((st = plan_launch(precision, BL.n_tasks, &cfg, true, loop, shared)) != FK_OK) return st;
 
-    std::vector<int64_t> task_off(n + 1, 0), block_off(n + 1, 0);
     int64_t station_base = 0;
     auto* descs = reinterpret_cast<fk::BatchDesc*>(ws + BL.desc);
-    hipError_t e = fk::launch_zero_queue(reinterpret_cast<unsigned long long*>(ws + BL.queue), stream);
+    uint32_t* status = reinterpret_cast<uint32_t*>(ws + BL.status);
+    auto* queue = reinterpret_cast<unsigned long long*>(ws + BL.queue);
+    hipError_t e = fk::launch_zero_queue(queue, stream, status, strict ? FK_FLAG_STRICT : 0u);
     if (e != hipSuccess) return fail(FK_EDEVICE, "queue reset launch failed: %s", hipGetErrorString(e));
     for (int32_t m = 0; m < n; ++m) {
         const fk_problem& P = probs[m];
-        const Layout& L = BL.per[m];
-        char* pb = ws + BL.base[m];
+        const Layout L = make_layout(P.kind, P.n_stations, &P.params, 0);
         fk::BatchDesc D;
         std::memset(&D, 0, sizeof D);
-        fill_common(D.c, P.kind, P.stations, P.n_stations, &P.box, &P.params, L, pb);
-        D.c.queue = nullptr;
+        fill_common(D.c, P.kind, P.stations, P.n_stations, &P.box, &P.params, L, nullptr);
         if (precision == FK_F64) fill_source_f64(D.s64, &P.source);
         else fill_source_f32(D.s32, &P.source);
         fill_bc(D.bc, &P.bc);
-        D.values = reinterpret_cast<double*>(pb + L.values);
-        D.partials = reinterpret_cast<fk::Partial*>(pb + L.partials);
         D.out = out + P.out_offset;
         D.n_chunks = L.n_chunks;
-        D.task_base = task_off[m];
-        D.block_base = block_off[m];
+        D.task_base = BL.tasks[m];
+        D.block_base = BL.pairs[m];
         D.station_base = station_base;
-        task_off[m + 1] = task_off[m] + L.n_tasks;
-        block_off[m + 1] = block_off[m] + P.n_stations * L.n_chunks;
         station_base += P.n_stations;
         e = fk::launch_write_words(reinterpret_cast<uint64_t*>(descs + m), reinterpret_cast<const uint64_t*>(&D),
                                    (int64_t)(sizeof D / 8), stream);
         if (e != hipSuccess) return fail(FK_EDEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
     }
     e = fk::launch_write_words(reinterpret_cast<uint64_t*>(ws + BL.task_off),
-                               reinterpret_cast<const uint64_t*>(task_off.data()), n + 1, stream);
+                               reinterpret_cast<const uint64_t*>(BL.tasks.data()), n + 1, stream);
     if (e == hipSuccess)
         e = fk::launch_write_words(reinterpret_cast<uint64_t*>(ws + BL.block_off),
-                                   reinterpret_cast<const uint64_t*>(block_off.data()), n + 1, stream);
+                                   reinterpret_cast<const uint64_t*>(BL.pairs.data()), n + 1, stream);
     if (e != hipSuccess) return fail(FK_EDEVICE, "offset upload failed: %s", hipGetErrorString(e));
 
     A.desc = descs;
     A.task_off = reinterpret_cast<const int64_t*>(ws + BL.task_off);
     A.block_off = reinterpret_cast<const int64_t*>(ws + BL.block_off);
-    A.queue = reinterpret_cast<unsigned long long*>(ws + BL.queue);
-    A.n_tasks = BL.n_tasks;
+    A.queue = queue;
+    A.exits = reinterpret_cast<fk::ExitRecord*>(ws + BL.exits);
+    A.steps = reinterpret_cast<uint32_t*>(ws + BL.steps);
+    A.values = BL.records ? reinterpret_cast<double*>(ws + BL.values) : nullptr;
+    A.partials = reinterpret_cast<fk::Partial*>(ws + BL.partials);
+    A.status = status;
     A.n_problems = n;
-    A.grab = cfg.grab;
-    A.total_waves = (uint32_t)((int64_t)cfg.grid * cfg.block / 64);
     A.precision = precision;
     A.chunk = kChunk;
 
-    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
-    const bool timed = timing_begin(&ev, stream);
-    e = fk::launch_batch_walk(A, cfg, stream, loop, shared);
-    if (timed) timing_end(ev, stream);
-    if (e != hipSuccess) return fail(FK_EDEVICE, "batch walk launch failed: %s", hipGetErrorString(e));
-    e = fk::launch_batch_reduce(A, BL.n_blocks, BL.n_stations, stream);
+    bool first = true;
+    st = for_each_slice(BL.shapes, BL.held, [&](const Slice& sl) -> fk_status {
+        hipError_t le = hipSuccess;
+        if (!first) le = fk::launch_zero_queue(queue, stream);
+        first = false;
+        if (le != hipSuccess) return fail(FK_EDEVICE, "queue reset launch failed: %s", hipGetErrorString(le));
+        fk::LaunchCfg cfg;
+        fk_status ps = plan_launch(precision, sl.t1 - sl.t0, &cfg, true, loop, shared);
+        if (ps != FK_OK) return ps;
+        A.task0 = sl.t0;
+        A.n_tasks = sl.t1 - sl.t0;
+        A.q0 = sl.q0;
+        A.grab = cfg.grab;
+        A.total_waves = (uint32_t)((int64_t)cfg.grid * cfg.block / 64);
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        const bool timed = timing_begin(&ev, stream);
+        le = fk::launch_batch_walk(A, cfg, stream, loop, shared);
+        if (timed) timing_end(ev, stream);
+        if (le != hipSuccess) return fail(FK_EDEVICE, "batch walk launch failed: %s", hipGetErrorString(le));
+        le = fk::launch_batch_chunks(A, sl.q1 - sl.q0, stream);
+        if (le != hipSuccess) return fail(FK_EDEVICE, "batch reduction launch failed: %s", hipGetErrorString(le));
+        return FK_OK;
+    });
+    if (st != FK_OK) return st;
+    e = fk::launch_batch_stations(A, BL.n_stations, stream);
     if (e != hipSuccess) return fail(FK_EDEVICE, "batch reduction launch failed: %s", hipGetErrorString(e));
     return FK_OK;
 }
@@ -667,6 +828,8 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
     if ((st = check_bc(bc)) != FK_OK) return st;
     if ((st = check_domain(box, p, bc)) != FK_OK) return st;
     if (!src->rho) return fail(FK_EINVAL, "the adjoint needs a voxel grid (source.rho is NULL)");
+    if (p->slice_walks != 0)
+        return fail(FK_EINVAL, "the adjoint replays a record-mode forward solve (slice_walks must be 0)");
     if (!grad_rho) return fail(FK_EINVAL, "grad_rho is NULL");
     const AdjLayout AL = make_adj_layout(n_stations, src);
     hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -766,8 +929,9 @@ fk_status fk_batch_layout(const fk_problem* problems, int32_t n_problems, int32_
     if (st != FK_OK) return st;
     if (m < 0 || m >= n_problems) return fail(FK_EINVAL, "problem index %d out of range", m);
     const BatchLayout B = make_batch_layout(problems, n_problems);
-    if (values_offset) *values_offset = B.base[m] + B.per[m].values;
-    if (steps_offset) *steps_offset = B.base[m] + B.per[m].steps;
+    if (!B.records) return fail(FK_EINVAL, "per-walk records are kept only with slice_walks = 0");
+    if (values_offset) *values_offset = B.values + sizeof(double) * (size_t)B.tasks[m];
+    if (steps_offset) *steps_offset = B.steps + sizeof(uint32_t) * (size_t)B.tasks[m];
     return FK_OK;
 }
 
@@ -790,9 +954,25 @@ fk_status fk_workspace_layout(int32_t kind, int64_t n_stations, const fk_params*
     fk_status st = check_params(kind, n_stations, params);
     if (st != FK_OK) return st;
     const Layout L = make_layout(kind, n_stations, params);
+    if (!L.records) return fail(FK_EINVAL, "per-walk records are kept only with slice_walks = 0");
     if (values_offset) *values_offset = L.values;
     if (steps_offset) *steps_offset = L.steps;
     if (total_bytes) *total_bytes = L.total;
+    return FK_OK;
+}
+
+fk_status fk_workspace_status(const void* workspace, uint32_t* flags, void* hip_stream)
+{
+    if (!workspace) return fail(FK_EINVAL, "workspace is NULL");
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    uint32_t word = 0;
+    hipError_t e = hipMemcpyAsync(&word, workspace, sizeof word, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(FK_EDEVICE, "reading the status word failed: %s", hipGetErrorString(e));
+    if (flags) *flags = word;
+    if (word & FK_FLAG_NONFINITE) return fail(FK_ENONFINITE, "a walk sample was NaN or infinite (flags 0x%x)", word);
+    if ((word & FK_FLAG_STRICT) && (word & FK_FLAG_TRUNCATED))
+        return fail(FK_ETRUNC, "strict solve: walks hit max_steps or started outside (flags 0x%x)", word);
     return FK_OK;
 }
 
@@ -1039,6 +1219,7 @@ const char* fk_status_string(int32_t status)
     case FK_EDEVICE: return "HIP runtime error";
     case FK_ETRUNC: return "walks hit max_steps";
     case FK_EUNSUPPORTED: return "size limit exceeded";
+    case FK_ENONFINITE: return "a walk sample was not finite";
     default: return "unknown status";
     }
 }

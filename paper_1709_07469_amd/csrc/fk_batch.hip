@@ -10,13 +10,12 @@
 //     the single-problem reduction.
 #include <hip/hip_runtime.h>
 
-#include "fk_device.hpp"
+#include "fk_stats.hpp"
 
 namespace fk {
 
 namespace {
 
-constexpr uint32_t kCapFlag = 0x80000000u;
 constexpr int kWords = 256;   // 2 KiB of payload per write launch
 
 struct Words {
@@ -28,134 +27,34 @@ __global__ void write_words_kernel(uint64_t* dst, const Words w, int n)
     for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = w.v[i];
 }
 
-// Largest m with off[m] <= t (off[0] = 0, off[n] = total > t).
-__device__ __forceinline__ int find_problem(const int64_t* off, int n, int64_t t)
-{
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= t) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // ---------------------------------------------------------------------------
-// Batched reduction: the blocks of all problems in one launch; block b finds
-// its problem by binary search over the block prefix sums.  Same arithmetic
-// and order as the single-problem reduction.
+// Batched reduction: the pairs of all problems in one launch; block b takes
+// global pair q0 + b and finds its problem by binary search over the pair
+// prefix sums.  Same arithmetic and order as the single-problem reduction.
 // ---------------------------------------------------------------------------
-constexpr int kReduceBlock = 256;
-
-struct Acc {
-    double n, mean, m2;
-    int64_t sum_steps, max_steps, n_trunc;
-};
-
-__device__ __forceinline__ void merge(Acc& a, const Acc& b)
-{
-    a.sum_steps += b.sum_steps;
-    a.max_steps = b.max_steps > a.max_steps ? b.max_steps : a.max_steps;
-    a.n_trunc += b.n_trunc;
-    if (b.n == 0.0) return;
-    if (a.n == 0.0) {
-        a.n = b.n;
-        a.mean = b.mean;
-        a.m2 = b.m2;
-        return;
-    }
-    const double n = a.n + b.n;
-    const double d = b.mean - a.mean;
-    const double f = b.n / n;
-    a.mean = a.mean + d * f;
-    a.m2 = a.m2 + b.m2 + d * d * a.n * f;
-    a.n = n;
-}
-
-__device__ __forceinline__ double batch_sample(const BatchDesc& D, int64_t j, uint32_t steps, const DataTables& tb)
-{
-    double v = __builtin_nan("");
-    if ((steps & kCapFlag) == 0) {
-        const ExitRecord r = D.c.exits[j];
-        const double e[3] = {r.x, r.y, r.z};
-        v = boundary_value(D.bc, D.c.lo, D.c.hi, D.c.G, e, tb) - D.c.w * r.S;
-    }
-    D.values[j] = v;
-    return v;
-}
-
 __global__ void __launch_bounds__(kReduceBlock) batch_chunk_kernel(const BatchArgs B)
 {
-    const int64_t gb = blockIdx.x;
-    const int m = find_problem(B.block_off, B.n_problems, gb);
+    const int64_t gq = B.q0 + blockIdx.x;
+    const int m = find_problem(B.block_off, B.n_problems, gq);
     const BatchDesc& D = B.desc[m];
-    const int64_t b = gb - B.block_off[m];
+    const int64_t b = gq - B.block_off[m];
     const int64_t N = D.c.N;
     const int64_t s = b / D.n_chunks;
     const int64_t c = b - s * D.n_chunks;
     const int64_t i0 = c * B.chunk;
     const int64_t i1 = (i0 + B.chunk < N) ? i0 + B.chunk : N;
-    const double two_h = 2.0 * D.c.h;
 
     DataTables tb{nullptr, nullptr};
     if (D.bc.kind == FK_BC_PRISMS) tb = fill_data_tables();     // one problem per block: uniform
 
-    Acc a{0.0, 0.0, 0.0, 0, 0, 0};
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kReduceBlock) {
-        double v;
-        uint32_t st;
-        bool capped;
-        if (D.c.npair == 2) {
-            const int64_t j = 2 * (s * N + i);
-            const uint32_t sp = D.c.steps[j], sm = D.c.steps[j + 1];
-            capped = ((sp | sm) & kCapFlag) != 0;
-            st = (sp & ~kCapFlag) + (sm & ~kCapFlag);
-            const double up = batch_sample(D, j, sp, tb);
-            const double um = batch_sample(D, j + 1, sm, tb);
-            v = (up - um) / two_h;
-        } else {
-            const int64_t j = s * N + i;
-            const uint32_t sp = D.c.steps[j];
-            capped = (sp & kCapFlag) != 0;
-            st = sp & ~kCapFlag;
-            v = batch_sample(D, j, sp, tb);
-        }
-        a.sum_steps += st;
-        a.max_steps = (int64_t)st > a.max_steps ? (int64_t)st : a.max_steps;
-        if (capped) {
-            a.n_trunc += 1;
-        } else {
-            a.n += 1.0;
-            const double d = v - a.mean;
-            a.mean += d / a.n;
-            a.m2 += d * (v - a.mean);
-        }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        Acc o;
-        o.n = __shfl_down(a.n, off);
-        o.mean = __shfl_down(a.mean, off);
-        o.m2 = __shfl_down(a.m2, off);
-        o.sum_steps = __shfl_down(a.sum_steps, off);
-        o.max_steps = __shfl_down(a.max_steps, off);
-        o.n_trunc = __shfl_down(a.n_trunc, off);
-        if ((int)__lane_id() < off) merge(a, o);
-    }
-    __shared__ Acc waves[kReduceBlock / 64];
-    if (__lane_id() == 0) waves[threadIdx.x >> 6] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Acc t = waves[0];
-        for (int w = 1; w < kReduceBlock / 64; ++w) merge(t, waves[w]);
-        Partial& p = D.partials[b];
-        p.n = t.n;
-        p.mean = t.mean;
-        p.m2 = t.m2;
-        p.sum_steps = t.sum_steps;
-        p.max_steps = t.max_steps;
-        p.n_trunc = t.n_trunc;
-    }
+    const int64_t rec0 = B.task_off[m] + s * N * D.c.npair - B.task0;
+    const PairSpan P{B.exits, B.steps, B.values ? B.values + B.task0 : nullptr, rec0, i0, i1, D.c.npair,
+                     2.0 * D.c.h};
+    auto data = [&](const ExitRecord& r) {
+        const double e[3] = {r.x, r.y, r.z};
+        return boundary_value(D.bc, D.c.lo, D.c.hi, D.c.G, e, tb) - D.c.w * r.S;
+    };
+    reduce_pair(P, data, B.partials + gq, B.status);
 }
 
 // Thread g handles station g of the concatenated station list (problems in
@@ -172,22 +71,7 @@ __global__ void __launch_bounds__(64) batch_station_kernel(const BatchArgs B, in
     }
     const BatchDesc& D = B.desc[lo];
     const int64_t s = g - D.station_base;
-    Acc a{0.0, 0.0, 0.0, 0, 0, 0};
-    for (int64_t c = 0; c < D.n_chunks; ++c) {
-        const Partial& p = D.partials[s * D.n_chunks + c];
-        const Acc b{p.n, p.mean, p.m2, p.sum_steps, p.max_steps, p.n_trunc};
-        merge(a, b);
-    }
-    fk_stat o;
-    o.n = (int64_t)a.n;
-    o.mean = a.n > 0.0 ? a.mean : __builtin_nan("");
-    o.var = a.n > 1.0 ? a.m2 / (a.n - 1.0) : __builtin_nan("");
-    o.se = a.n > 1.0 ? sqrt(o.var / a.n) : __builtin_nan("");
-    o.sum_steps = a.sum_steps;
-    o.max_steps = a.max_steps;
-    o.n_trunc = a.n_trunc;
-    o.mean_steps = (double)a.sum_steps / (double)D.c.N;
-    D.out[s] = o;
+    D.out[s] = finish_station(B.partials + D.block_base + s * D.n_chunks, D.n_chunks, D.c.N);
 }
 
 }  // namespace
@@ -205,13 +89,17 @@ hipError_t launch_write_words(uint64_t* dst, const uint64_t* host_words, int64_t
     return hipSuccess;
 }
 
-hipError_t launch_batch_reduce(const BatchArgs& a, int64_t n_blocks, int64_t n_station_threads, hipStream_t stream)
+hipError_t launch_batch_chunks(const BatchArgs& a, int64_t n_pairs, hipStream_t stream)
 {
-    hipLaunchKernelGGL(batch_chunk_kernel, dim3((unsigned)n_blocks), dim3(kReduceBlock), 0, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_station_kernel, dim3((unsigned)((n_station_threads + 63) / 64)), dim3(64), 0, stream, a,
-                       n_station_threads);
+    if (n_pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_chunk_kernel, dim3((unsigned)n_pairs), dim3(kReduceBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stations(const BatchArgs& a, int64_t n_stations, hipStream_t stream)
+{
+    hipLaunchKernelGGL(batch_station_kernel, dim3((unsigned)((n_stations + 63) / 64)), dim3(64), 0, stream, a,
+                       n_stations);
     return hipGetLastError();
 }
 

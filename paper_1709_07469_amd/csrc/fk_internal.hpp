@@ -59,14 +59,17 @@ struct ExitRecord {
 
 // Task t of a solve is (station s, local path i, walk w):
 //   t = (s * N + i) * npair + w,  npair = 1 (potential) or 2 (g_z walks +h, -h).
+// A launch runs the tasks task0 .. task0 + n_tasks - 1 (all of them, or one
+// slice of a bounded workspace) and stores task t's record at t - task0.
 struct WalkCommon {
     const double* stations;    // device, n_stations x 3
-    ExitRecord* exits;         // device, n_tasks exit records
-    uint32_t* steps;           // device, n_tasks step counts (bit 31: capped)
+    ExitRecord* exits;         // device, the launch's exit records
+    uint32_t* steps;           // device, the launch's step counts (bit 31: capped)
     unsigned long long* queue; // device, next unclaimed task
     int64_t n_stations;
     int64_t N;
-    int64_t n_tasks;
+    int64_t n_tasks;           // tasks of this launch
+    int64_t task0;             // first task of this launch
     int64_t path_offset;
     int64_t max_steps;
     double lo[3], hi[3];
@@ -120,16 +123,21 @@ struct Partial {
     int64_t n_trunc;
 };
 
+// The reduction of the (station, chunk) pairs q0 .. q0 + gridDim - 1 (pair
+// q = s * n_chunks + c) whose walks' records start at task task0.
 struct ReduceArgs {
     const ExitRecord* exits;
-    double* values;            // per-walk samples written here
+    double* values;            // per-walk samples written here (record mode), or null
     const uint32_t* steps;
-    Partial* partials;
+    Partial* partials;         // one per pair, all pairs of the solve
     fk_stat* out;
+    uint32_t* status;          // the workspace's status word (FK_FLAG_* bits)
     int64_t n_stations;
     int64_t N;
     int64_t chunk;             // samples per partial
     int64_t n_chunks;          // partials per station
+    int64_t q0;                // first pair of this launch
+    int64_t task0;             // task of the first record
     int32_t npair;
     int32_t pad0;
     double two_h;
@@ -140,29 +148,35 @@ struct ReduceArgs {
 };
 
 // One problem of a batched solve, as the batch kernels see it (in device
-// memory, written by the descriptor kernels).  Task t of the batch belongs to
-// problem m when task_base[m] <= t < task_base[m+1]; its local task is
-// t - task_base[m], laid out as in WalkCommon.
+// memory, written by the descriptor kernels).  Tasks and (station, chunk) pairs of a batch are numbered across its
+// problems in order: global task T = task_off[m] + t, global pair
+// Q = block_off[m] + q.  Records, per-walk values and partials are indexed
+// by these global numbers (records from the launch's first task).
 struct BatchDesc {
-    WalkCommon c;              // queue unused
+    WalkCommon c;              // queue, exits, steps, n_tasks, task0 unused
     SourceF64 s64;
     SourceF32 s32;
     BoundaryArgs bc;
-    double* values;
-    Partial* partials;
     fk_stat* out;              // this problem's first station result
     int64_t n_chunks;
     int64_t task_base;
-    int64_t block_base;        // first reduction block of this problem
+    int64_t block_base;        // first reduction block (pair) of this problem
     int64_t station_base;      // first station of this problem in the batch's station numbering
 };
 
 struct BatchArgs {
     BatchDesc* desc;           // device, n_problems
     const int64_t* task_off;   // device, n_problems + 1 prefix sums of tasks
-    const int64_t* block_off;  // device, n_problems + 1 prefix sums of reduction blocks
+    const int64_t* block_off;  // device, n_problems + 1 prefix sums of (station, chunk) pairs
     unsigned long long* queue;
-    int64_t n_tasks;
+    ExitRecord* exits;         // device, records of tasks task0 .. task0 + n_tasks - 1
+    uint32_t* steps;
+    double* values;            // device, per-walk samples by global task (record mode), or null
+    Partial* partials;         // device, one per global pair
+    uint32_t* status;          // the workspace's status word
+    int64_t n_tasks;           // tasks of this launch
+    int64_t task0;             // first global task of this launch
+    int64_t q0;                // first global pair of this reduction launch
     int32_t n_problems;
     int32_t grab;
     uint32_t total_waves;
@@ -182,7 +196,10 @@ struct LaunchCfg {
 };
 
 // Host launchers (one translation unit per kernel family).
-hipError_t launch_zero_queue(unsigned long long* queue, hipStream_t stream);
+// Clears the queue's claim counters; with status non-null also sets the
+// status word to `flags` (the start of a solve).
+hipError_t launch_zero_queue(unsigned long long* queue, hipStream_t stream, uint32_t* status = nullptr,
+                             uint32_t flags = 0);
 hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream_t stream, bool adjoint = false);
 hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cfg, hipStream_t stream,
                            bool adjoint = false);
@@ -191,7 +208,9 @@ hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cf
 hipError_t launch_fill_zero(int64_t* p, int64_t n, hipStream_t stream);
 hipError_t launch_adjoint_combine(const int64_t* counts, int64_t n_stations, int64_t nvox, const double* grad_out,
                                   const fk_stat* fwd, double scale, double* grad_rho, hipStream_t stream);
-hipError_t launch_reduce(const ReduceArgs& a, hipStream_t stream);
+// The chunk partials of pairs a.q0 .. a.q0 + n_pairs - 1; then, when
+// finish is set, every station's result from all its partials.
+hipError_t launch_reduce(const ReduceArgs& a, int64_t n_pairs, bool finish, hipStream_t stream);
 // loop: 0 box stepping loop, 1 with the ball exit test, 2 with the
 // Brownian-bridge test too
 hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop = 0, bool adjoint = false);
@@ -203,7 +222,8 @@ hipError_t launch_stream_blocks(const uint32_t* ctr, int64_t n, uint32_t key0, u
 // and the batched reduction.
 hipError_t launch_write_words(uint64_t* dst, const uint64_t* host_words, int64_t n_words, hipStream_t stream);
 hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, int loop, bool shared);
-hipError_t launch_batch_reduce(const BatchArgs& a, int64_t n_blocks, int64_t n_station_threads, hipStream_t stream);
+hipError_t launch_batch_chunks(const BatchArgs& a, int64_t n_pairs, hipStream_t stream);
+hipError_t launch_batch_stations(const BatchArgs& a, int64_t n_stations, hipStream_t stream);
 hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, int loop = 0, bool shared = false);
 
 }  // namespace fk

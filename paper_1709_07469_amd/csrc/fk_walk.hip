@@ -35,13 +35,12 @@
 
 #include <type_traits>
 
-#include "fk_device.hpp"
+#include "fk_stats.hpp"
 
 namespace fk {
 
 namespace {
 
-constexpr uint32_t kCapFlag = 0x80000000u;
 constexpr int kMaxWaves = 4;        // 256 threads per block at most
 
 // In a batch of problems with separate sources the task queue is split into
@@ -55,9 +54,10 @@ constexpr int kMaxWaves = 4;        // 256 threads per block at most
 // and stripes that end on long walks lengthen the drain.
 constexpr uint32_t kStripes = 8;
 
-__global__ void zero_queue_kernel(unsigned long long* q)
+__global__ void zero_queue_kernel(unsigned long long* q, uint32_t* status, uint32_t flags)
 {
     if (threadIdx.x < kStripes) q[threadIdx.x] = 0ull;
+    if (status && threadIdx.x == 0) *status = flags;
 }
 
 __device__ __forceinline__ uint64_t first_lane_u64(uint64_t v)
@@ -149,18 +149,6 @@ __device__ __forceinline__ uint64_t refill(Pool& pool, const Queue& Q, bool acti
     pool.next += taken;
     pool.started += (int64_t)taken;
     return mine;
-}
-
-// Largest m with off[m] <= t (off[0] = 0, off[n] = total > t).
-__device__ __forceinline__ int find_problem(const int64_t* off, int n, int64_t t)
-{
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= t) lo = mid;
-        else hi = mid;
-    }
-    return lo;
 }
 
 struct TaskInfo {
@@ -472,7 +460,9 @@ constexpr bool loop_grid(int loop) { return (loop & kLoopGrid) != 0; }
 template <bool F64, bool KAHAN, bool ADJ, int LOOP>
 struct Walker {
     using T = typename Prec<F64>::T;
-    uint64_t task;
+    uint64_t rec;    // the walk's record slot (its task minus the launch's first task)
+    ExitRecord* exits;
+    uint32_t* steps_out;
     T x0, x1, x2, rp;
     double S;        // trapezoid sum (FP64 accumulation)
     float Sf, Sc;    // Kahan sum and compensation
@@ -741,8 +731,8 @@ struct Walker {
                 }
             }
             const double sum = (!F64 && KAHAN) ? ((double)Sf - (double)Sc) : S;
-            C.exits[task] = ExitRecord{e[0], e[1], e[2], sum};
-            C.steps[task] = n | (capped ? kCapFlag : 0u);
+            exits[rec] = ExitRecord{e[0], e[1], e[2], sum};
+            steps_out[rec] = n | (capped ? kCapFlag : 0u);
         }
         active = false;
     }
@@ -829,7 +819,14 @@ __device__ __forceinline__ void walk_body(const Args& A)
     Pool pool = start_pool<STRIPES>(Q);
     Walker<F64, KAHAN, ADJ, LOOP> W;
     W.active = false;
-    W.task = 0;
+    W.rec = 0;
+    if constexpr (BATCH) {
+        W.exits = A.exits;
+        W.steps_out = A.steps;
+    } else {
+        W.exits = A.c.exits;
+        W.steps_out = A.c.steps;
+    }
     W.x0 = W.x1 = W.x2 = W.rp = T(0);
     W.S = 0.0;
     W.Sf = W.Sc = 0.0f;
@@ -851,30 +848,32 @@ __device__ __forceinline__ void walk_body(const Args& A)
         const uint64_t got = refill<STRIPES>(pool, Q, W.active);
         if (got != ~0ull) {
             const WalkCommon* Cp;
-            uint64_t t = got;
+            uint64_t t;
             if constexpr (BATCH) {
-                const int m = find_problem(A.task_off, A.n_problems, (int64_t)got);
+                const int64_t T = A.task0 + (int64_t)got;
+                const int m = find_problem(A.task_off, A.n_problems, T);
                 const BatchDesc& D = A.desc[m];
-                t = got - (uint64_t)A.task_off[m];
+                t = (uint64_t)(T - A.task_off[m]);
                 if constexpr (SHARED)
                     P.load(D.c, shared_source<F64>(A));
                 else
                     P.load(D.c, SourceOf<F64>::get(D));
                 Cp = &D.c;
             } else {
+                t = (uint64_t)A.c.task0 + got;
                 Cp = &A.c;
             }
             const WalkCommon& C = *Cp;
             const TaskInfo ti = decode(C, t);
-            W.task = t;
+            W.rec = got;
             const bool inside = strictly_inside(C, ti.x0);
             if (ADJ && (!inside || forward_capped(C, t))) {
                 // excluded in the forward solve: contributes nothing
             } else if (!ADJ && !inside) {
                 // a start point on or outside the boundary yields no sample
                 const double q = __builtin_nan("");
-                C.exits[t] = ExitRecord{q, q, q, q};
-                C.steps[t] = kCapFlag;
+                W.exits[got] = ExitRecord{q, q, q, q};
+                W.steps_out[got] = kCapFlag;
             } else {
                 W.x0 = (T)ti.x0[0];
                 W.x1 = (T)ti.x0[1];
@@ -1107,9 +1106,9 @@ __global__ void __launch_bounds__(256, loop_exit(LOOP)   ? 1
 
 }  // namespace
 
-hipError_t launch_zero_queue(unsigned long long* queue, hipStream_t stream)
+hipError_t launch_zero_queue(unsigned long long* queue, hipStream_t stream, uint32_t* status, uint32_t flags)
 {
-    hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(64), 0, stream, queue);
+    hipLaunchKernelGGL(zero_queue_kernel, dim3(1), dim3(64), 0, stream, queue, status, flags);
     return hipGetLastError();
 }
 

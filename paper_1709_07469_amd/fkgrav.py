@@ -20,10 +20,11 @@ import threading
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-# FKGRAV_LIB names another build of the library (e.g. for A/B timing)
-LIB_PATH = os.environ.get("FKGRAV_LIB") or os.path.join(_PKG, "libfkgrav.so")
+LIB_PATH = os.path.join(_PKG, "libfkgrav.so")
 
 FK_OK, FK_EINVAL, FK_EDOMAIN, FK_EWORKSPACE, FK_EDEVICE, FK_ETRUNC, FK_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FK_ENONFINITE = -7
+FK_FLAG_TRUNCATED, FK_FLAG_NONFINITE, FK_FLAG_STRICT = 1, 2, 256
 FK_F64, FK_MIXED_F64ACC, FK_MIXED_KAHAN = 0, 1, 2
 FK_EXIT_OVERSHOOT, FK_EXIT_INTERSECT, FK_EXIT_BRIDGE = 0, 1, 2
 FK_DOMAIN_BOX, FK_DOMAIN_BALL = 0, 1
@@ -59,7 +60,7 @@ class fk_params(C.Structure):
     _fields_ = [("paths_per_station", C.c_int64), ("dt", C.c_double), ("seed", C.c_uint64), ("G", C.c_double),
                 ("h", C.c_double), ("precision", C.c_int32), ("exit_rule", C.c_int32), ("pairing", C.c_int32),
                 ("strict", C.c_int32), ("max_steps", C.c_int64), ("problem_id", C.c_uint32), ("domain", C.c_int32),
-                ("path_offset", C.c_int64)]
+                ("path_offset", C.c_int64), ("slice_walks", C.c_int64)]
 
 
 class fk_stat(C.Structure):
@@ -99,6 +100,8 @@ def lib():
             L.fk_workspace_bytes.restype = sz
             L.fk_workspace_layout.argtypes = [i32, i64, p, p, p, p]
             L.fk_workspace_layout.restype = i32
+            L.fk_workspace_status.argtypes = [p, p, p]
+            L.fk_workspace_status.restype = i32
             L.fk_check_stations.argtypes = [p, i64, p, i32, p]
             L.fk_check_stations.restype = i32
             for nm in ("fk_solve_potential", "fk_solve_gz"):
@@ -173,6 +176,18 @@ def fk_workspace_layout(kind: int, n_stations: int, params: fk_params):
     _check(lib().fk_workspace_layout(int(kind), int(n_stations), C.byref(params), C.byref(v), C.byref(s),
                                      C.byref(t)))
     return v.value, s.value, t.value
+
+
+def fk_workspace_status(workspace, stream=None):
+    """Waits for the stream and returns (status, flags) of the last solve run
+    in the workspace: status FK_OK, FK_ETRUNC (strict solve with capped
+    walks) or FK_ENONFINITE, flags the FK_FLAG_* bits.  Does not raise on
+    those two statuses."""
+    f = C.c_uint32()
+    st = lib().fk_workspace_status(_ptr(workspace), C.byref(f), _stream_handle(stream))
+    if st not in (FK_OK, FK_ETRUNC, FK_ENONFINITE):
+        _check(st)
+    return int(st), int(f.value)
 
 
 def fk_check_stations(stations_host: np.ndarray, box: fk_box, kind: int, params: fk_params) -> None:
@@ -370,11 +385,12 @@ def make_params(prob, **over) -> fk_params:
     p.precision = int(g("precision", 0))
     p.exit_rule = int(g("exit_rule", 0))
     p.pairing = int(g("pairing", 0))
-    p.strict = 0
+    p.strict = int(g("strict", 0))
     p.max_steps = int(g("max_steps", (1 << 31) - 1))
     p.problem_id = int(g("problem_id", 0))
     p.domain = int(g("domain", 0))
     p.path_offset = int(g("path_offset", 0))
+    p.slice_walks = int(g("slice_walks", 0))
     return p
 
 

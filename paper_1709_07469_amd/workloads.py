@@ -78,6 +78,11 @@ class Problem:
     max_steps: int = 1 << 30
     problem_id: int = 0
     path_offset: int = 0
+    # Reporting and workspace options of the HIP library (no effect on what
+    # is computed): strict = report capped walks as an error; slice_walks > 0
+    # = bounded workspace, walks run in slices of at most that many.
+    strict: int = 0
+    slice_walks: int = 0
     name: str = ""
     # Prisms that the voxel grid represents exactly; kept for closed-form
     # targets only and never part of the source.

@@ -194,7 +194,8 @@ def test_workspace_layout_and_launch_settings():
     prm = F.make_params(pr)
     v, s, t = F.fk_workspace_layout(0, 64, prm)
     T = 64 * pr.paths_per_station
-    assert v == 0 and s >= 8 * T and s % 256 == 0 and t >= s + 4 * T + 32 * T
+    # the status block, then the per-walk values, step counts and exit records
+    assert v == 256 and s >= v + 8 * T and s % 256 == 0 and t >= s + 4 * T + 32 * T
     v1, s1, t1 = F.fk_workspace_layout(1, 64, prm)
     assert s1 >= 16 * T and t1 > t
     assert F.fk_workspace_bytes(0, 64, prm) == t
@@ -222,3 +223,55 @@ def test_product_path_refuses_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         F.solve(W.cfg1(10), 0)
+
+
+def test_bounded_workspace_sizes():
+    # slice_walks > 0: the workspace holds one slice's records (36 B per walk)
+    # and 48 B per (station, chunk) pair, whatever the walk count
+    pr = W.cfg2()
+    rec = F.make_params(pr)
+    full = F.fk_workspace_bytes(1, 64, rec)
+    sl = F.make_params(pr, slice_walks=1 << 20)
+    small = F.fk_workspace_bytes(1, 64, sl)
+    pairs = 64 * ((pr.paths_per_station + 8191) // 8192)
+    assert 0 < small < full
+    assert small >= 36 * (1 << 20) + 48 * pairs
+    assert small <= 36 * (1 << 20) + 48 * pairs + 5 * 256
+    big = F.make_params(pr.replace(paths_per_station=1 << 31), slice_walks=1 << 20)
+    assert F.fk_workspace_bytes(1, 64, big) < 36 * (1 << 20) + 48 * 64 * (1 << 18) + 5 * 256
+    # per-walk records exist in record mode only
+    with pytest.raises(F.FkError) as e:
+        F.fk_workspace_layout(1, 64, sl)
+    assert e.value.status == F.FK_EINVAL
+    # a slice holds at least one chunk of 8192 paths per walk of a pair
+    for kind, bad in ((0, 8191), (1, 16383), (0, -1)):
+        assert F.fk_workspace_bytes(kind, 64, F.make_params(pr, slice_walks=bad)) == 0
+    assert F.fk_workspace_bytes(0, 64, F.make_params(pr, slice_walks=8192)) > 0
+
+
+def test_batch_slice_walks_must_agree():
+    from paper_1709_07469_amd import workloads as Wl
+    a = Wl.cfg1(100)
+    b = Wl.cfg1(100).replace(slice_walks=1 << 16)
+    arr = (F.fk_problem * 2)()
+    keep = []
+    for m, pr in enumerate((a, b)):
+        _, box, src, bc, prm, k = _host_problem(slice_walks=pr.slice_walks)
+        keep.append(k)
+        arr[m].kind = 0
+        arr[m].stations = 4096
+        arr[m].n_stations = 8
+        arr[m].box = box
+        arr[m].source = src
+        arr[m].bc = bc
+        arr[m].params = prm
+        arr[m].out_offset = 8 * m
+    assert F.lib().fk_batch_workspace_bytes(arr, 2) == 0
+    assert "slice_walks" in F.lib().fk_last_error().decode()
+
+
+def test_workspace_status_rejects_null():
+    st = F.lib().fk_workspace_status(None, None, None)
+    assert st == F.FK_EINVAL
+    assert F.fk_status_string(F.FK_ENONFINITE) != "unknown status"
+    assert F.fk_status_string(F.FK_ETRUNC) != "unknown status"

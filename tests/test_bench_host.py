@@ -1,9 +1,10 @@
-"""Host logic of bench.py (no GPU): the derived metrics and the rules that
-attach recorded counter data to the bench line only for the kernel sources
-they were taken on."""
+"""Host logic of bench.py (no GPU): the derived metrics, the roofline entry
+and the rule that attaches recorded counter data to the bench line only for
+the kernel sources it was taken on."""
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 import bench
@@ -23,39 +24,66 @@ def test_station_estimates_per_s_hand_example():
     assert bench.station_estimates_per_s([], 1e6, rel) is None
 
 
-def test_algorithmic_ops_are_the_sum_of_the_parts():
-    c = bench.ISSUE_COST
-    assert bench.algorithmic_ops_per_step("f64") == pytest.approx(
-        1.5 * c["philox_block"] + 1.5 * c["box_muller_pair_f64"] + c["step_f64"])
-    assert bench.algorithmic_ops_per_step("mixed") == pytest.approx(
-        0.75 * c["philox_block"] + 1.5 * c["box_muller_pair_f32"] + c["step_f32_f64sum"])
+def test_algorithmic_flop_count():
+    # 1.5 Box-Muller pairs of 8, three position FMAs, three index FMAs and
+    # the trapezoid term's two additions
+    assert bench.ALGO_FLOP_PER_STEP == 1.5 * 8 + 3 * 2 + 3 * 2 + 2
     assert bench.PEAK_LANE_OPS == 256 * 4 * 16 * 2.4e9
 
 
+def test_roofline_entry_follows_the_algorithmic_work(monkeypatch):
+    monkeypatch.setattr(bench, "COUNTERS", {})
+    r = bench.roofline("x", "mixed", 6e11, 2000.0, 1.2e9, grid_bytes=32 << 20)
+    rate = 6e11 / 2.0
+    assert r["achieved"] == pytest.approx(26 * rate / 1e12)
+    assert r["peak"] == pytest.approx(157.3) and r["unit"] == "TFLOP/s" and r["bound"] == "alu"
+    assert r["frac"] == pytest.approx(26 * rate / 157.3e12)
+    assert r["algorithmic_bytes_per_launch"] == 1.2e9 * 36 + (32 << 20)
+    assert r["traffic"] is None and r["counters"] is None
+    r64 = bench.roofline("x", "f64", 6e11, 2000.0, 1.2e9)
+    assert r64["peak"] == pytest.approx(78.6) and r64["frac"] == pytest.approx(26 * rate / 78.6e12)
+
+
 def test_recorded_counters_apply_only_to_their_sources(monkeypatch):
-    monkeypatch.setattr(bench, "PMC_BYTES", {"sources_sha256": "abc", "fetch_scale": 2.0, "write_scale": 1.0,
-                                             "f64_batched": {"fetch_kib": 1.0, "write_kib": 3.0}})
-    monkeypatch.setattr(bench, "VALU_COUNTERS", {"sources_sha256": "abc", "f64_batched": {
-        "valu_lane_instr_per_step": 250.0, "valu_busy": 0.97, "fp64_flop_per_step": 100.0,
-        "fp32_flop_per_step": 2.0}})
+    monkeypatch.setattr(bench, "COUNTERS", {"sources_sha256": "abc", "k": {
+        "fetch_kib": 1.0, "write_kib": 3.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "valu_lane_instr_per_step": 100.0, "valu_busy": 1.08, "fp64_flop_per_step": 2.0,
+        "fp32_flop_per_step": 20.0}})
     monkeypatch.setattr(bench, "sources_sha256", lambda: "abc")
-    assert bench.measured_traffic("f64", "batched") == 1024 * (2.0 * 1.0 + 3.0)
-    c = bench.valu_counters("f64", "batched", 1e11)
-    assert c["fp64_tflops"] == pytest.approx(10.0)
-    assert c["fp64_frac_of_peak"] == pytest.approx(1e13 / 78.6e12)
-    assert c["fp32_frac_of_peak"] == pytest.approx(2e11 / 157.3e12)
-    # another launch form, or the sources changed since: no figure at all
-    assert bench.measured_traffic("f64", "separate") is None
-    assert bench.valu_counters("mixed", "batched", 1e11) is None
+    r = bench.roofline("k", "mixed", 1e11, 1000.0, 1e6)
+    assert r["traffic"] == 1024 * (2.0 * 1.0 + 3.0)
+    c = r["counters"]
+    assert c["valu_busy"] == 1.0                       # clamped
+    assert c["valu_issue_frac"] == pytest.approx(100.0 * 1e11 / bench.PEAK_LANE_OPS)
+    assert c["fp32_frac_of_peak"] == pytest.approx(20.0 * 1e11 / 157.3e12)
+    assert c["fp64_frac_of_peak"] == pytest.approx(2.0 * 1e11 / 78.6e12)
+    # another kernel, or the sources changed since: no figure at all
+    assert bench.roofline("other", "mixed", 1e11, 1000.0, 1e6)["counters"] is None
     monkeypatch.setattr(bench, "sources_sha256", lambda: "changed")
-    assert bench.measured_traffic("f64", "batched") is None
-    assert bench.valu_counters("f64", "batched", 1e11) is None
+    r = bench.roofline("k", "mixed", 1e11, 1000.0, 1e6)
+    assert r["traffic"] is None and r["counters"] is None
 
 
-def test_sources_hash_covers_the_walk_kernel_sources():
+def test_closed_form_error():
+    e = bench.closed_form_error([1.0, 2.2, -3.0], [0.1, 0.1, 0.5], [1.1, 2.0, -3.0])
+    assert e["stations"] == 3
+    assert e["max_abs_z"] == pytest.approx(2.0)
+    assert e["rms_z"] == pytest.approx(np.sqrt((1.0 + 4.0 + 0.0) / 3))
+    assert e["frac_within_4se"] == 1.0
+    assert e["max_rel_err"] == pytest.approx(0.1)
+
+
+def test_host_cpu_description():
+    c = bench.host_cpu()
+    assert c["model"] and c["hardware_threads"] and c["hardware_threads"] >= 1
+    assert c["physical_cores"] is None or 1 <= c["physical_cores"] <= c["hardware_threads"]
+
+
+def test_sources_hash_covers_the_kernel_sources():
     h = bench.sources_sha256()
     assert len(h) == 64 and int(h, 16) >= 0
-    assert any(p.endswith("fk_walk.hip") for p in bench.TRAFFIC_SOURCES)
+    for name in ("fk_walk.hip", "fk_device.hpp", "fk_batch.hip", "fk_stats.hpp"):
+        assert any(p.endswith(name) for p in bench.TRAFFIC_SOURCES)
 
 
 def test_more_than_one_gpu_is_refused():
