@@ -262,6 +262,27 @@ fk_status fk_solve_gz(const double *stations, int64_t n_stations, const fk_box *
                       const fk_source *source, const fk_boundary *bc, const fk_params *params,
                       fk_stat *out, void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * potential (kind 0) or g_z (kind 1) solve of fk_solve_potential /
+ * fk_solve_gz without a workspace argument.  Its scratch is a device array of
+ * 64 MiB inside the library, one per GPU, allocated with the library's code
+ * object and held until the process ends; the call itself allocates nothing.
+ * It runs as a bounded-workspace solve (no per-walk records are kept) with
+ * slices as large as the array allows (at most params->slice_walks when that
+ * is set), and gives the results of fk_solve_potential / fk_solve_gz bit for
+ * bit.  The array holds every (station, chunk) pair's 48-byte partial, so a
+ * solve with more than about 1.38 million pairs (n_stations *
+ * ceil(N / 8192)) is rejected with FK_EUNSUPPORTED before anything is
+ * launched.  Every call on a GPU uses the same array: calls that overlap on
+ * one GPU (on different streams, or from several threads) race and must not
+ * be issued; each call clears the claim counters it needs.  The status word
+ * of fk_workspace_status is not reachable for these solves; fk_stat.n_trunc
+ * and NaN means carry the same information. */
+fk_status fk_solve_static(int32_t kind, const double *stations, int64_t n_stations, const fk_box *box,
+                          const fk_source *source, const fk_boundary *bc, const fk_params *params,
+                          fk_stat *out, void *hip_stream);
+
 /* Batched solve (one persistent launch): n_problems independent problems --
  * each with its own stations (DEVICE), box, density, boundary data and
  * parameters -- share one work queue, so problems of very different cost keep

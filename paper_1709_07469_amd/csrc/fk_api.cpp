@@ -225,6 +225,7 @@ fk_status for_each_slice(const std::vector<Shape>& shapes, int64_t budget, F&& f
         } else {
             close();
             const int64_t run = budget / (kChunk * p.npair);
+            if (run < 1) return fail(FK_EINVAL, "a slice must hold one chunk of 8192 paths per walk of a pair");
             for (int64_t s = 0; s < p.S && st == FK_OK; ++s)
                 for (int64_t c0 = 0; c0 < p.n_chunks && st == FK_OK; c0 += run) {
                     const int64_t c1 = std::min(p.n_chunks, c0 + run);
@@ -889,7 +890,83 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Solves without a workspace argument: their scratch is this file's device
+// array, one per GPU, held until the process ends.
+// ---------------------------------------------------------------------------
+static constexpr size_t kScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// The device address of scratch on each device (the array's host-side name
+// is not a device address), looked up once per device with it current.
+void* g_scratch[64] = {nullptr};
+
+fk_status scratch_of_current_device(char** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(FK_EDEVICE, "hipGetDevice failed");
+    if (dev < 0 || dev >= 64) return fail(FK_EUNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(FK_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch[dev] = ptr;
+    }
+    *out = static_cast<char*>(g_scratch[dev]);
+    return FK_OK;
+}
+
+// The bounded layout that fits kScratchBytes: every pair's partial, the
+// status and queue blocks, and as many records as the rest holds (no more
+// than params->slice_walks when that is set).
+fk_status static_layout(int32_t kind, int64_t n_stations, const fk_params* p, Layout* L)
+{
+    const int64_t npair = kind == 1 ? 2 : 1;
+    const Layout base = make_layout(kind, n_stations, p, 1);       // one record held
+    const size_t fixed = base.total - 2 * 256;                     // minus the record arrays' rounding slack
+    const size_t per = sizeof(uint32_t) + sizeof(fk::ExitRecord);
+    if (fixed + per * (size_t)(kChunk * npair) > kScratchBytes)
+        return fail(FK_EUNSUPPORTED, "solve too large for the %zu-byte scratch: %lld (station, chunk) pairs "
+                                     "(at most about %zu)", kScratchBytes, (long long)base.n_pairs,
+                    (kScratchBytes - per * (size_t)(kChunk * npair)) / sizeof(fk::Partial));
+    int64_t held = (int64_t)((kScratchBytes - fixed) / per);
+    if (p->slice_walks > 0 && p->slice_walks < held) held = p->slice_walks;
+    for (; held >= kChunk * npair; held -= 64) {   // the regions' 256-byte rounding may take a few records
+        *L = make_layout(kind, n_stations, p, held);
+        if (L->total <= kScratchBytes) return FK_OK;
+    }
+    return fail(FK_EUNSUPPORTED, "solve too large for the %zu-byte scratch", kScratchBytes);
+}
+
+fk_status solve_static(int32_t kind, const double* stations, int64_t n_stations, const fk_box* box,
+                       const fk_source* src, const fk_boundary* bc, const fk_params* p, fk_stat* out,
+                       void* hip_stream)
+{
+    fk_status st = check_solve(kind, stations, n_stations, box, src, bc, p, out);
+    if (st != FK_OK || n_stations == 0) return st;
+    Layout L;
+    if ((st = static_layout(kind, n_stations, p, &L)) != FK_OK) return st;
+    char* ws = nullptr;
+    if ((st = scratch_of_current_device(&ws)) != FK_OK) return st;
+    return run_solve(kind, stations, n_stations, box, src, bc, p, out, ws, L,
+                     reinterpret_cast<hipStream_t>(hip_stream), false);
+}
+
+}  // namespace
+
 extern "C" {
+
+fk_status fk_solve_static(int32_t kind, const double* stations, int64_t n_stations, const fk_box* box,
+                          const fk_source* source, const fk_boundary* bc, const fk_params* params, fk_stat* out,
+                          void* hip_stream)
+{
+    if (kind != 0 && kind != 1) return fail(FK_EINVAL, "kind must be 0 (potential) or 1 (g_z), got %d", kind);
+    return solve_static(kind, stations, n_stations, box, source, bc, params, out, hip_stream);
+}
 
 size_t fk_adjoint_workspace_bytes(int64_t n_stations, const fk_source* source)
 {

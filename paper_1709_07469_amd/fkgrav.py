@@ -107,6 +107,8 @@ def lib():
             for nm in ("fk_solve_potential", "fk_solve_gz"):
                 getattr(L, nm).argtypes = [p, i64, p, p, p, p, p, p, sz, p]
                 getattr(L, nm).restype = i32
+            L.fk_solve_static.argtypes = [i32, p, i64, p, p, p, p, p, p]
+            L.fk_solve_static.restype = i32
             L.fk_batch_workspace_bytes.argtypes = [p, i32]
             L.fk_batch_workspace_bytes.restype = sz
             L.fk_batch_layout.argtypes = [p, i32, i32, p, p]
@@ -210,6 +212,14 @@ def fk_solve_potential(stations, box, source, bc, params, out, workspace, stream
 
 def fk_solve_gz(stations, box, source, bc, params, out, workspace, stream=None) -> None:
     _solve_call("fk_solve_gz", stations, box, source, bc, params, out, workspace, stream)
+
+
+def fk_solve_static(kind, stations, box, source, bc, params, out, stream=None) -> None:
+    """fk_solve_potential (kind 0) / fk_solve_gz (kind 1) without a workspace:
+    the library's per-GPU scratch array serves instead (no allocation)."""
+    n = int(stations.shape[0]) if stations is not None else 0
+    _check(lib().fk_solve_static(int(kind), _ptr(stations), n, C.byref(box), C.byref(source), C.byref(bc),
+                                 C.byref(params), _ptr(out), _stream_handle(stream)))
 
 
 def fk_batch_workspace_bytes(problems) -> int:
