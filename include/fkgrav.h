@@ -366,12 +366,17 @@ fk_status fk_moving_average(const double *values, const double *se, int64_t n, i
 /* Launch settings of the walk kernels (the autotuner's knobs).  block: threads
  * per block (64..256, multiple of 64); blocks_per_cu: resident blocks per
  * compute unit (0 = as many as fit); grab: largest number of walks a
- * wavefront takes from the global queue at once (1..64). */
+ * wavefront takes from the global queue at once (1..64); adjoint_table: how
+ * the adjoint gathers its occupation weights in LDS before they reach the
+ * global counts -- 0: a dense per-station table when the grid has at most
+ * 32768 voxels (512-thread blocks working through the stations one at a
+ * time), else the hashed block table; 1: the hashed block table always.
+ * Settings never change results. */
 typedef struct {
     int32_t block;
     int32_t blocks_per_cu;
     int32_t grab;
-    int32_t pad0;
+    int32_t adjoint_table;
 } fk_launch;
 
 fk_status fk_set_launch(int32_t precision, const fk_launch *launch);

@@ -807,14 +807,26 @@ struct AdjLayout {
     size_t counts, queue, total;
 };
 
+// The counts [S][nvox], then the claim counters: the queue's stripes, or
+// one per station for the dense-table instance.
 AdjLayout make_adj_layout(int64_t n_stations, const fk_source* src)
 {
     AdjLayout A{};
     A.nvox = (int64_t)src->n[0] * src->n[1] * src->n[2];
     A.counts = 0;
     A.queue = align256(sizeof(int64_t) * (size_t)(n_stations * A.nvox));
-    A.total = align256(A.queue + 256);
+    A.total = align256(A.queue + std::max<size_t>(256, sizeof(uint64_t) * (size_t)n_stations));
     return A;
+}
+
+bool adjoint_dense(int precision, int64_t n_stations, int64_t nvox)
+{
+    int table = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        table = g_launch[precision].adjoint_table;
+    }
+    return table == 0 && nvox <= fk::kAdjDenseVoxels && n_stations <= fk::kAdjDenseMaxStations;
 }
 
 fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, const fk_box* box, const fk_source* src,
@@ -850,8 +862,26 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
     int64_t* counts = reinterpret_cast<int64_t*>(ws + AL.counts);
 
     fk::LaunchCfg cfg;
-    if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p, nullptr), false, true)) != FK_OK)
+    const bool dense = adjoint_dense(p->precision, n_stations, AL.nvox);
+    if (dense) {
+        // 512-thread blocks, as many as the LDS allows per compute unit
+        int dev = 0, bpc = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return fail(FK_EDEVICE, "hipGetDevice failed");
+        const int cus = compute_units(dev);
+        if (fk::walk_occupancy(p->precision, fk::kAdjDenseBlock, &bpc, loop_kind(p, nullptr), true, true) !=
+                hipSuccess || bpc <= 0 || cus <= 0)
+            return fail(FK_EDEVICE, "occupancy query failed for the dense adjoint");
+        fk_launch l;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            l = g_launch[p->precision];
+        }
+        cfg.block = fk::kAdjDenseBlock;
+        cfg.grid = cus * bpc;
+        cfg.grab = l.grab;
+    } else if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p, nullptr), false, true)) != FK_OK) {
         return st;
+    }
     fk::WalkCommon C;
     fill_common(C, kind, stations, n_stations, box, p, L, nullptr);
     C.exits = nullptr;
@@ -864,7 +894,9 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
     C.nvox = AL.nvox;
 
     hipError_t e = fk::launch_fill_zero(counts, n_stations * AL.nvox, stream);
-    if (e == hipSuccess) e = fk::launch_zero_queue(C.queue, stream);
+    if (e == hipSuccess)
+        e = dense ? fk::launch_fill_zero(reinterpret_cast<int64_t*>(C.queue), n_stations, stream)
+                  : fk::launch_zero_queue(C.queue, stream);
     if (e != hipSuccess) return fail(FK_EDEVICE, "adjoint set-up launch failed: %s", hipGetErrorString(e));
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     const bool timed = timing_begin(&ev, stream);
@@ -872,12 +904,12 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
         fk::WalkArgsF64 A;
         A.c = C;
         fill_source_f64(A.src, src);
-        e = fk::launch_walk_f64(A, cfg, stream, true);
+        e = fk::launch_walk_f64(A, cfg, stream, true, dense);
     } else {
         fk::WalkArgsF32 A;
         A.c = C;
         fill_source_f32(A.src, src);
-        e = fk::launch_walk_f32(A, p->precision == FK_MIXED_KAHAN, cfg, stream, true);
+        e = fk::launch_walk_f32(A, p->precision == FK_MIXED_KAHAN, cfg, stream, true, dense);
     }
     if (timed) timing_end(ev, stream);
     if (e != hipSuccess) return fail(FK_EDEVICE, "adjoint walk launch failed: %s", hipGetErrorString(e));
@@ -1143,7 +1175,7 @@ fk_status fk_autotune(int32_t kind, const double* stations, int64_t n_stations, 
             for (int gi = 0; gi < 3 && st == FK_OK; ++gi) {
                 {
                     std::lock_guard<std::mutex> lk(g_mu);
-                    g_launch[precision] = fk_launch{blocks[bi], bpcs[pi], grabs[gi], 0};
+                    g_launch[precision] = fk_launch{blocks[bi], bpcs[pi], grabs[gi], keep.adjoint_table};
                 }
                 float ms = 0.0f;
                 // one untimed run, then one timed run
@@ -1160,7 +1192,7 @@ fk_status fk_autotune(int32_t kind, const double* stations, int64_t n_stations, 
                 }
                 if (ms < best_t) {
                     best_t = ms;
-                    best_l = fk_launch{blocks[bi], bpcs[pi], grabs[gi], 0};
+                    best_l = fk_launch{blocks[bi], bpcs[pi], grabs[gi], keep.adjoint_table};
                 }
             }
         }
@@ -1245,9 +1277,10 @@ fk_status fk_set_launch(int32_t precision, const fk_launch* launch)
         return fail(FK_EINVAL, "block must be a multiple of 64 in [64, 256]");
     if (launch->blocks_per_cu < 0 || launch->blocks_per_cu > 64) return fail(FK_EINVAL, "blocks_per_cu must lie in [0, 64]");
     if (launch->grab < 1 || launch->grab > 64) return fail(FK_EINVAL, "grab must lie in [1, 64]");
+    if (launch->adjoint_table < 0 || launch->adjoint_table > 1) return fail(FK_EINVAL, "adjoint_table must be 0 or 1");
     std::lock_guard<std::mutex> lk(g_mu);
     g_launch[precision] = *launch;
-    g_launch[precision].pad0 = 0;
+
     return FK_OK;
 }
 

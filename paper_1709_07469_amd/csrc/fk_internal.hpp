@@ -200,9 +200,17 @@ struct LaunchCfg {
 // status word to `flags` (the start of a solve).
 hipError_t launch_zero_queue(unsigned long long* queue, hipStream_t stream, uint32_t* status = nullptr,
                              uint32_t flags = 0);
-hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream_t stream, bool adjoint = false);
+// adjoint: the replay that scatters occupation weights; dense: its instance
+// with per-station dense LDS tables (grids of at most kAdjDenseVoxels voxels,
+// blocks of kAdjDenseBlock threads, one claim counter per station in the
+// queue region).
+constexpr int64_t kAdjDenseVoxels = 32768;
+constexpr int64_t kAdjDenseMaxStations = 65536;
+constexpr int kAdjDenseBlock = 1024;
+hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream_t stream, bool adjoint = false,
+                           bool dense = false);
 hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cfg, hipStream_t stream,
-                           bool adjoint = false);
+                           bool adjoint = false, bool dense = false);
 // Adjoint helpers: zero the count array; combine counts into the
 // vector-Jacobian product grad_rho[v] = sum_s coef_s * counts[s][v].
 hipError_t launch_fill_zero(int64_t* p, int64_t n, hipStream_t stream);
@@ -213,7 +221,8 @@ hipError_t launch_adjoint_combine(const int64_t* counts, int64_t n_stations, int
 hipError_t launch_reduce(const ReduceArgs& a, int64_t n_pairs, bool finish, hipStream_t stream);
 // loop: 0 box stepping loop, 1 with the ball exit test, 2 with the
 // Brownian-bridge test too
-hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop = 0, bool adjoint = false);
+hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop = 0, bool adjoint = false,
+                          bool dense = false);
 hipError_t launch_stream_blocks(const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t* words,
                                 double* z64, float* z32, hipStream_t stream);
 

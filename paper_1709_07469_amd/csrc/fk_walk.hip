@@ -263,17 +263,48 @@ __device__ __forceinline__ void adj_emit(uint32_t* tab, int64_t* counts, int64_t
     }
 }
 
-// Run-length coalesced scatter of one walk's signed trapezoid weights.
+// Dense station tables: when a grid has at most kDenseVoxels voxels, each
+// block of the adjoint works on one station at a time and adds its walks'
+// weights into a plain int32 count per voxel in LDS (128 KiB: an LDS atomic
+// add, no key, no eviction), flushed to the global counts when the block
+// moves on to another station.  A weight of 2^19 or more goes straight to
+// the global counts; a count that reaches +-2^30 is taken out of the table by
+// an atomic exchange and moved there too (concurrent adds of the block's
+// 1024 threads, each below 2^19, cannot carry it past 2^31 meanwhile).
+constexpr int kDenseVoxels = (int)kAdjDenseVoxels;
+constexpr int64_t kDenseDirect = 1ll << 19;
+constexpr int64_t kDenseLimit = 1ll << 30;
+static_assert(kAdjDenseBlock * kDenseDirect + kDenseLimit < (1ll << 31), "a dense count must stay within int32");
+
+__device__ __forceinline__ void dense_emit(int* tab, int64_t* counts, int64_t row, int64_t v, int64_t w)
+{
+    if (w >= kDenseDirect || w <= -kDenseDirect) {
+        global_add(counts, row + v, w);
+        return;
+    }
+    const int old = atomicAdd(&tab[v], (int)w);
+    const int64_t now = (int64_t)old + w;
+    if (now >= kDenseLimit || now <= -kDenseLimit) global_add(counts, row + v, (int64_t)atomicExch(&tab[v], 0));
+}
+
+// Run-length coalesced scatter of one walk's signed trapezoid weights, into
+// the block's hashed table or (DENSE) its dense station table.
+template <bool DENSE>
 struct Scatter {
     int64_t* counts;            // the problem's counts
-    uint32_t* tab;              // the block's table
+    void* tab;                  // the block's table
     int64_t row;                // station offset into counts
     int64_t v;                  // pending voxel (-1: none)
     int64_t c;                  // pending weight
     int64_t sign;
     __device__ __forceinline__ void flush()
     {
-        if (v >= 0 && c != 0) adj_emit(tab, counts, row + v, c);
+        if (v >= 0 && c != 0) {
+            if constexpr (DENSE)
+                dense_emit(static_cast<int*>(tab), counts, row, v, c);
+            else
+                adj_emit(static_cast<uint32_t*>(tab), counts, row + v, c);
+        }
         c = 0;
     }
     __device__ __forceinline__ void add(int64_t voxel, int64_t weight)
@@ -457,7 +488,7 @@ constexpr int loop_exit(int loop) { return loop & 3; }
 constexpr bool loop_grid(int loop) { return (loop & kLoopGrid) != 0; }
 
 // One lane's walk.
-template <bool F64, bool KAHAN, bool ADJ, int LOOP>
+template <bool F64, bool KAHAN, bool ADJ, int LOOP, bool DENSE = false>
 struct Walker {
     using T = typename Prec<F64>::T;
     uint64_t rec;    // the walk's record slot (its task minus the launch's first task)
@@ -469,7 +500,7 @@ struct Walker {
     uint32_t n, k, sctr, pctr;
     bool active;
     bool deep;       // the current point lies delta inside every face (bridge test)
-    Scatter sc;
+    Scatter<DENSE> sc;
 
     // delta inside every face (ball: |x - c|^2 <= (R - delta)^2)
     __device__ __forceinline__ static bool deep_inside(const LaneProblem<F64>& P, T y0, T y1, T y2, T d2)
@@ -741,15 +772,27 @@ struct Walker {
 // ---------------------------------------------------------------------------
 // The kernel body.
 // ---------------------------------------------------------------------------
-template <bool F64, bool KAHAN, bool ADJ, bool BATCH, int LOOP, bool SHARED, class Args>
+// DENSE (adjoint only): blocks of kAdjDenseBlock threads with a dense
+// per-station table,
+// working through the stations one at a time (each station's tasks have
+// their own claim counter; a block starts on station blockIdx mod S and,
+// when its station's tasks are all claimed and its walks done, flushes the
+// table and moves on to the next station with unclaimed tasks).
+template <bool F64, bool KAHAN, bool ADJ, bool BATCH, int LOOP, bool SHARED, bool DENSE, class Args>
 __device__ __forceinline__ void walk_body(const Args& A)
 {
     using T = typename Prec<F64>::T;
     constexpr int NPB = Prec<F64>::kNormals;
     constexpr int MACRO = Prec<F64>::kMacro;
+    // Drain rounds need a buffer per wavefront; the dense instance runs
+    // without them (its LDS holds the table), so its last walks of a station
+    // step in ordinary macro-steps.
+    constexpr bool DRAIN = !DENSE;
+    constexpr int TAIL_WAVES = DRAIN ? kMaxWaves : 1;
+    static_assert(!DENSE || (ADJ && !BATCH), "dense tables are the adjoint's");
 
-    __shared__ int tail_lane[kMaxWaves][64];
-    __shared__ T tail_z[kMaxWaves][3 * 64][NPB];
+    __shared__ int tail_lane[TAIL_WAVES][64];
+    __shared__ T tail_z[TAIL_WAVES][3 * 64][NPB];
     const BmTables* bmt = nullptr;
     if constexpr (F64) {
         BmTables* t = bm_tables();
@@ -817,7 +860,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
     // registers it costs more than it gains (both measured)
     constexpr bool kHeld = !loop_grid(LOOP) && !(F64 && BATCH);
     Pool pool = start_pool<STRIPES>(Q);
-    Walker<F64, KAHAN, ADJ, LOOP> W;
+    Walker<F64, KAHAN, ADJ, LOOP, DENSE> W;
     W.active = false;
     W.rec = 0;
     if constexpr (BATCH) {
@@ -832,18 +875,32 @@ __device__ __forceinline__ void walk_body(const Args& A)
     W.Sf = W.Sc = 0.0f;
     W.n = W.k = W.sctr = W.pctr = 0;
     W.deep = false;
-    W.sc = Scatter{nullptr, nullptr, 0, -1, 0, 1};
-    uint32_t* adj_tab = nullptr;
-    if constexpr (ADJ) {
+    W.sc = Scatter<DENSE>{nullptr, nullptr, 0, -1, 0, 1};
+    void* adj_tab = nullptr;
+    int* dirty = nullptr;       // dense: set when the block starts a walk of its station
+    if constexpr (ADJ && !DENSE) {
         static_assert(!BATCH, "the adjoint runs single-problem launches");
         __shared__ uint32_t tab[kAdjSlots];
         for (int i = threadIdx.x; i < kAdjSlots; i += blockDim.x) tab[i] = 0u;
         __syncthreads();
         adj_tab = tab;
     }
+    if constexpr (DENSE) {
+        __shared__ int dtab[kDenseVoxels];
+        __shared__ int dflag;
+        for (int i = threadIdx.x; i < kDenseVoxels; i += blockDim.x) dtab[i] = 0;
+        if (threadIdx.x == 0) dflag = 0;
+        __syncthreads();
+        adj_tab = dtab;
+        dirty = &dflag;
+    }
     const int wave = threadIdx.x >> 6;
     const int lane = (int)__lane_id();
+    uint64_t task_base = 0;   // task of queue index 0
+    if constexpr (!BATCH) task_base = (uint64_t)A.c.task0;
 
+    // The wavefront's walks until its queue is used up and they are done.
+    auto run_waves = [&]() {
     for (;;) {
         const uint64_t got = refill<STRIPES>(pool, Q, W.active);
         if (got != ~0ull) {
@@ -860,7 +917,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
                     P.load(D.c, SourceOf<F64>::get(D));
                 Cp = &D.c;
             } else {
-                t = (uint64_t)A.c.task0 + got;
+                t = task_base + got;
                 Cp = &A.c;
             }
             const WalkCommon& C = *Cp;
@@ -885,6 +942,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
                 W.S = 0.0;
                 W.Sf = W.Sc = 0.0f;
                 if (ADJ) {
+                    if (DENSE) __hip_atomic_store(dirty, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     W.sc.counts = C.counts;
                     W.sc.tab = adj_tab;
                     W.sc.row = (int64_t)ti.s * C.nvox;
@@ -910,7 +968,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
         }
         const int m = __popcll(live);
 
-        if (pool.exhausted) {
+        if (DRAIN && pool.exhausted) {
             // ---- drain round: the queue is empty, so every lane generates
             // three Philox blocks for the live walks of its wavefront (block
             // slot g = r * m + w holds block r of live walk w), and each live
@@ -1037,11 +1095,58 @@ __device__ __forceinline__ void walk_body(const Args& A)
         });
         if (done) W.finish(P, z, at, how);
     }
-    if constexpr (ADJ) {
+    };
+
+    if constexpr (DENSE) {
+        __shared__ int next_station;
+        const int64_t S = A.c.n_stations;
+        const uint64_t per = (uint64_t)A.c.N * (uint64_t)A.c.npair;   // tasks of one station
+        const int64_t nvox = A.c.nvox;
+        int* tab = static_cast<int*>(adj_tab);
+        const uint32_t waves_per_station = A.c.total_waves / (uint32_t)S > 0 ? A.c.total_waves / (uint32_t)S : 1u;
+        if (threadIdx.x == 0) next_station = (int)(blockIdx.x % (uint32_t)S);
+        __syncthreads();
+        for (;;) {
+            const int s = next_station;
+            if (s < 0) break;
+            Q = Queue{A.c.queue + s, per, (uint32_t)A.c.grab, waves_per_station};
+            pool = start_pool<1>(Q);
+            task_base = (uint64_t)s * per;
+            run_waves();
+            __syncthreads();    // the block's walks of station s are done
+            if (*dirty) {
+                for (int64_t v = threadIdx.x; v < nvox; v += blockDim.x) {
+                    const int c = tab[v];
+                    if (c != 0) {
+                        global_add(A.c.counts, (int64_t)s * nvox + v, c);
+                        tab[v] = 0;
+                    }
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                *dirty = 0;
+                int nxt = -1;
+                for (int64_t k = 1; k <= S; ++k) {
+                    const int c = (int)((s + k) % S);
+                    if (__hip_atomic_load(A.c.queue + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < per) {
+                        nxt = c;
+                        break;
+                    }
+                }
+                next_station = nxt;
+            }
+            __syncthreads();
+        }
+    } else {
+        run_waves();
+    }
+    if constexpr (ADJ && !DENSE) {
         // every wavefront has left the loop: the table's entries go out
         __syncthreads();
+        const uint32_t* tab = static_cast<const uint32_t*>(adj_tab);
         for (int i = threadIdx.x; i < kAdjSlots; i += blockDim.x) {
-            const uint32_t e = adj_tab[i];
+            const uint32_t e = tab[i];
             const int64_t c = adj_count(e);
             if (adj_key(e) != 0 && c != 0) global_add(A.c.counts, (int64_t)adj_key(e) - 1, c);
         }
@@ -1091,7 +1196,16 @@ __global__ void __launch_bounds__(256, ADJ                ? kAdjBlocksPerCu
                                                          : FK_F32_BLOCKS_PER_CU)
     walk_kernel(const typename std::conditional<F64, WalkArgsF64, WalkArgsF32>::type A)
 {
-    walk_body<F64, KAHAN, ADJ, false, LOOP, false>(A);
+    walk_body<F64, KAHAN, ADJ, false, LOOP, false, false>(A);
+}
+
+// The adjoint with dense station tables: one block of kAdjDenseBlock threads
+// per CU (the 128 KiB table takes most of the CU's 160 KiB of LDS).
+template <bool F64, bool KAHAN, int LOOP>
+__global__ void __launch_bounds__(kAdjDenseBlock, 1)
+    adjoint_dense_kernel(const typename std::conditional<F64, WalkArgsF64, WalkArgsF32>::type A)
+{
+    walk_body<F64, KAHAN, true, false, LOOP, false, true>(A);
 }
 
 template <bool F64, bool KAHAN, int LOOP, bool SHARED>
@@ -1101,7 +1215,7 @@ __global__ void __launch_bounds__(256, loop_exit(LOOP)   ? 1
                                                                       : FK_BATCH_F32_BLOCKS_PER_CU)
     batch_walk_kernel(const BatchArgs A)
 {
-    walk_body<F64, KAHAN, false, true, LOOP, SHARED>(A);
+    walk_body<F64, KAHAN, false, true, LOOP, SHARED, false>(A);
 }
 
 }  // namespace
@@ -1131,17 +1245,25 @@ void with_loop(int loop, F&& f)
 // The adjoint samples no density (it counts voxel visits), so its loop never
 // carries the grid bit.
 template <bool F64, bool KAHAN, bool ADJ, class A>
-void launch_walk(const A& a, int loop, const LaunchCfg& cfg, hipStream_t stream)
+void launch_walk(const A& a, int loop, const LaunchCfg& cfg, hipStream_t stream, bool dense)
 {
     with_loop(ADJ ? loop_exit(loop) : loop, [&](auto L) {
-        hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, decltype(L)::value>), dim3(cfg.grid), dim3(cfg.block), 0,
-                           stream, a);
+        if (ADJ && dense)
+            hipLaunchKernelGGL((adjoint_dense_kernel<F64, KAHAN, loop_exit(decltype(L)::value)>), dim3(cfg.grid),
+                               dim3(cfg.block), 0, stream, a);
+        else
+            hipLaunchKernelGGL((walk_kernel<F64, KAHAN, ADJ, decltype(L)::value>), dim3(cfg.grid), dim3(cfg.block),
+                               0, stream, a);
     });
 }
 
 template <int LOOP, bool ADJ>
-const void* walk_fn(int precision)
+const void* walk_fn(int precision, bool dense)
 {
+    if (ADJ && dense)
+        return precision == FK_F64 ? (const void*)adjoint_dense_kernel<true, false, loop_exit(LOOP)>
+             : precision == FK_MIXED_KAHAN ? (const void*)adjoint_dense_kernel<false, true, loop_exit(LOOP)>
+                                           : (const void*)adjoint_dense_kernel<false, false, loop_exit(LOOP)>;
     return precision == FK_F64 ? (const void*)walk_kernel<true, false, ADJ, LOOP>
          : precision == FK_MIXED_KAHAN ? (const void*)walk_kernel<false, true, ADJ, LOOP>
                                        : (const void*)walk_kernel<false, false, ADJ, LOOP>;
@@ -1178,40 +1300,41 @@ int loop_of(const WalkCommon& c, bool grid)
 
 }  // namespace
 
-hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream_t stream, bool adjoint)
+hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream_t stream, bool adjoint, bool dense)
 {
     const int loop = loop_of(a.c, a.src.has_grid != 0);
     if (adjoint)
-        launch_walk<true, false, true>(a, loop, cfg, stream);
+        launch_walk<true, false, true>(a, loop, cfg, stream, dense);
     else
-        launch_walk<true, false, false>(a, loop, cfg, stream);
+        launch_walk<true, false, false>(a, loop, cfg, stream, false);
     return hipGetLastError();
 }
 
-hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cfg, hipStream_t stream, bool adjoint)
+hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cfg, hipStream_t stream, bool adjoint,
+                           bool dense)
 {
     const int loop = loop_of(a.c, a.src.has_grid != 0);
     if (adjoint) {
         if (kahan)
-            launch_walk<false, true, true>(a, loop, cfg, stream);
+            launch_walk<false, true, true>(a, loop, cfg, stream, dense);
         else
-            launch_walk<false, false, true>(a, loop, cfg, stream);
+            launch_walk<false, false, true>(a, loop, cfg, stream, dense);
     } else {
         if (kahan)
-            launch_walk<false, true, false>(a, loop, cfg, stream);
+            launch_walk<false, true, false>(a, loop, cfg, stream, false);
         else
-            launch_walk<false, false, false>(a, loop, cfg, stream);
+            launch_walk<false, false, false>(a, loop, cfg, stream, false);
     }
     return hipGetLastError();
 }
 
-hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop, bool adjoint)
+hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop, bool adjoint, bool dense)
 {
     const void* fn = nullptr;
     if (adjoint)
-        with_loop(loop_exit(loop), [&](auto L) { fn = walk_fn<decltype(L)::value, true>(precision); });
+        with_loop(loop_exit(loop), [&](auto L) { fn = walk_fn<decltype(L)::value, true>(precision, dense); });
     else
-        with_loop(loop, [&](auto L) { fn = walk_fn<decltype(L)::value, false>(precision); });
+        with_loop(loop, [&](auto L) { fn = walk_fn<decltype(L)::value, false>(precision, false); });
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
 

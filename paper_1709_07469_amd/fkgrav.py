@@ -70,7 +70,8 @@ class fk_stat(C.Structure):
 
 
 class fk_launch(C.Structure):
-    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("grab", C.c_int32), ("pad0", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("grab", C.c_int32),
+                ("adjoint_table", C.c_int32)]
 
 
 class fk_problem(C.Structure):
@@ -305,14 +306,14 @@ def fk_moving_average(values, se=None, span: int = 5):
     return ov, oe
 
 
-def fk_set_launch(precision: int, block: int, blocks_per_cu: int = 0, grab: int = 32) -> None:
-    _check(lib().fk_set_launch(int(precision), C.byref(fk_launch(block, blocks_per_cu, grab, 0))))
+def fk_set_launch(precision: int, block: int, blocks_per_cu: int = 0, grab: int = 32, adjoint_table: int = 0) -> None:
+    _check(lib().fk_set_launch(int(precision), C.byref(fk_launch(block, blocks_per_cu, grab, adjoint_table))))
 
 
 def fk_get_launch(precision: int):
     l = fk_launch()
     _check(lib().fk_get_launch(int(precision), C.byref(l)))
-    return {"block": l.block, "blocks_per_cu": l.blocks_per_cu, "grab": l.grab}
+    return {"block": l.block, "blocks_per_cu": l.blocks_per_cu, "grab": l.grab, "adjoint_table": l.adjoint_table}
 
 
 def fk_timing_enable(on: bool) -> None:

@@ -201,7 +201,11 @@ def test_workspace_layout_and_launch_settings():
     assert F.fk_workspace_bytes(0, 64, prm) == t
     old = F.fk_get_launch(0)
     F.fk_set_launch(0, 128, 2, 16)
-    assert F.fk_get_launch(0) == {"block": 128, "blocks_per_cu": 2, "grab": 16}
+    assert F.fk_get_launch(0) == {"block": 128, "blocks_per_cu": 2, "grab": 16, "adjoint_table": 0}
+    F.fk_set_launch(0, 128, 2, 16, adjoint_table=1)
+    assert F.fk_get_launch(0)["adjoint_table"] == 1
+    with pytest.raises(F.FkError):
+        F.fk_set_launch(0, 128, 2, 16, adjoint_table=2)
     with pytest.raises(F.FkError):
         F.fk_set_launch(0, 96)
     with pytest.raises(F.FkError):
