@@ -530,58 +530,99 @@ __device__ __forceinline__ double atan_q(double n, double d, const AtanTable& A)
     return ((n < 0.0) != (d < 0.0)) ? -a : a;
 }
 
-// ln(a + r) with r = sqrt(a^2 + s), s > 0: for a < 0 the sum cancels, and
-// a + r = s / (r - a) is used instead (s times the reciprocal).  The
-// callers also evaluate terms they then discard (s = 0 or a = r = 0); their
-// argument is replaced by 1 so that the table lookup stays in range.
-__device__ __forceinline__ double log_shift(double a, double r, double s, const BmTables& T)
+// The argument of ln(w + r), r = sqrt(w^2 + s), as a quotient n / d free
+// of cancellation: (w + r) / 1 for w >= 0, and s / (r - w) for w < 0, where
+// the sum would cancel.
+struct Quot {
+    double n, d;
+};
+
+__device__ __forceinline__ Quot shift_quot(double w, double r, double s)
 {
-    const bool pos = a >= 0.0;
-    const double q = pos ? a + r : r - a;
-    double x = pos ? q : s * recip(q);
+    const bool pos = w >= 0.0;
+    return Quot{pos ? w + r : s, pos ? 1.0 : r - w};
+}
+
+// ln(A / B) for A = a.n / a.d and B = b.n / b.d, as one logarithm of
+// (a.n b.d) / (a.d b.n).  An argument that is not positive and finite --
+// only in terms the caller discards, whose prefactor is zero -- is replaced by
+// 1 so that the table lookup stays in range.
+__device__ __forceinline__ double ln_ratio(const Quot& a, const Quot& b, const BmTables& T)
+{
+    double x = (a.n * b.d) * recip(a.d * b.n);
     x = (x > 0.0 && x <= 0x1.fffffffffffffp+1023) ? x : 1.0;
     return ln_t(x, T);
+}
+
+// atan2(n, d), the angle of the point (d, n) in (-pi, pi]: atan(n / d) moved
+// by pi to the left half-plane.  n = d = 0 occurs only in discarded terms.
+__device__ __forceinline__ double atan2_q(double n, double d, const AtanTable& A)
+{
+    const double a = atan_q(n, d, A);
+    const double pi = 0x1.921fb54442d18p+1;
+    return d < 0.0 ? (n < 0.0 ? a - pi : a + pi) : a;
+}
+
+// F(X, Y, Z) below has the cyclic form sum over (u, v, w) of
+// u v ln(w + r) - (u^2 / 2) atan(v w / (u r)), (u, v, w) = (X, Y, Z), (Y, Z, X),
+// (Z, X, Y).  Along a prism edge only w changes, so the difference of one such
+// pair of terms between the edge's upper corner (w_u, r_u) and lower corner
+// (w_l, r_l) takes one logarithm and one arctangent:
+//   u v ln((w_u + r_u) / (w_l + r_l))
+//   - (u^2 / 2) atan2(u v (w_u r_l - w_l r_u), u^2 r_u r_l + v^2 w_u w_l)
+// (atan p - atan q = atan2(p - q, 1 + p q), here multiplied through by
+// u^2 r_u r_l > 0).  A term whose prefactor u v or u is zero vanishes.
+__device__ __forceinline__ double edge_terms(double u, double v, double wl, double wu, double rl, double ru, double u2,
+                                             double v2, const BmTables& T, const AtanTable& A)
+{
+    const double uv = u * v;
+    const double s = u2 + v2;
+    const double l = uv * ln_ratio(shift_quot(wu, ru, s), shift_quot(wl, rl, s), T);
+    const double t = 0.5 * u2 * atan2_q(uv * (wu * rl - wl * ru), u2 * (ru * rl) + v2 * (wu * wl), A);
+    return ((uv != 0.0) ? l : 0.0) - ((u != 0.0) ? t : 0.0);
 }
 
 // Newtonian integral of the unit-density prism [lo, hi] seen from p: the
 // alternating corner sum of
 //   XY ln(Z+r) + YZ ln(X+r) + ZX ln(Y+r)
 //   - X^2/2 atan(YZ/(Xr)) - Y^2/2 atan(ZX/(Yr)) - Z^2/2 atan(XY/(Zr))
-// with corner (X, Y, Z) = corner - p and sign + at the upper corner (Nagy,
-// Papp & Benedek 2000); a term whose prefactor is zero vanishes.  Every
-// term is evaluated and the vanishing ones are selected away (their
-// logarithm or quotient may be infinite), so the lanes of a wavefront --
-// whose exit points differ -- take no branches.
+// with corner (X, Y, Z) = corner - p and sign + at the corners with an odd
+// number of upper coordinates (Nagy, Papp & Benedek 2000); a term whose
+// prefactor is zero vanishes.  The corners are taken in pairs along each of
+// the 12 edges, each edge carrying the two terms whose prefactors stay fixed
+// along it (edge_terms): 8 square roots, 12 logarithms and 12 arctangents
+// instead of 24 of each, and no cancellation between the two corners' large
+// logarithms and angles.  Every term is evaluated and the vanishing ones
+// selected away (their logarithm or quotient may be infinite), so the lanes
+// of a wavefront -- whose exit points differ -- take no branches.
 __device__ inline double prism_newton(const double* q, double px, double py, double pz, const DataTables& tb)
 {
     const BmTables& T = *tb.bm;
     const AtanTable& A = *tb.at;
+    const double X[2] = {q[0] - px, q[3] - px};
+    const double Y[2] = {q[1] - py, q[4] - py};
+    const double Z[2] = {q[2] - pz, q[5] - pz};
+    const double X2[2] = {X[0] * X[0], X[1] * X[1]};
+    const double Y2[2] = {Y[0] * Y[0], Y[1] * Y[1]};
+    const double Z2[2] = {Z[0] * Z[0], Z[1] * Z[1]};
+    double r[2][2][2];   // r[i][j][k] at corner (X[i], Y[j], Z[k])
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) r[i][j][k] = sqrt(X2[i] + Y2[j] + Z2[k]);
     double v = 0.0;
 #pragma unroll
-    for (int corner = 0; corner < 8; ++corner) {
-        const double X = ((corner & 1) ? q[3] : q[0]) - px;
-        const double Y = ((corner & 2) ? q[4] : q[1]) - py;
-        const double Z = ((corner & 4) ? q[5] : q[2]) - pz;
-        const double X2 = X * X, Y2 = Y * Y, Z2 = Z * Z;
-        const double r = sqrt(X2 + Y2 + Z2);
-        const double XY = X * Y, YZ = Y * Z, ZX = Z * X;
-        double f = 0.0;
-        const double l1 = XY * log_shift(Z, r, X2 + Y2, T);
-        f += (XY != 0.0) ? l1 : 0.0;
-        const double l2 = YZ * log_shift(X, r, Y2 + Z2, T);
-        f += (YZ != 0.0) ? l2 : 0.0;
-        const double l3 = ZX * log_shift(Y, r, Z2 + X2, T);
-        f += (ZX != 0.0) ? l3 : 0.0;
-        const double t1 = 0.5 * X2 * atan_q(YZ, X * r, A);
-        f -= (X != 0.0) ? t1 : 0.0;
-        const double t2 = 0.5 * Y2 * atan_q(ZX, Y * r, A);
-        f -= (Y != 0.0) ? t2 : 0.0;
-        const double t3 = 0.5 * Z2 * atan_q(XY, Z * r, A);
-        f -= (Z != 0.0) ? t3 : 0.0;
-        // sign (-1)^(i+j+k) with index 1 = lower, 2 = upper corner: positive
-        // when the number of upper coordinates is odd
-        const int uppers = (corner & 1) + ((corner >> 1) & 1) + ((corner >> 2) & 1);
-        v += (uppers & 1) ? f : -f;
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            // an edge's upper corner has a + b + 1 upper coordinates: sign + when that is odd
+            double e = edge_terms(X[a], Y[b], Z[0], Z[1], r[a][b][0], r[a][b][1], X2[a], Y2[b], T, A);   // along z
+            e += edge_terms(Y[a], Z[b], X[0], X[1], r[0][a][b], r[1][a][b], Y2[a], Z2[b], T, A);          // along x
+            e += edge_terms(Z[a], X[b], Y[0], Y[1], r[b][0][a], r[b][1][a], Z2[a], X2[b], T, A);          // along y
+            v += ((a + b) & 1) ? -e : e;
+        }
     }
     return v;
 }
