@@ -62,3 +62,21 @@ def test_table1_shape_and_time_step_reading():
     # the paper's walk sqrt(2) W with step sqrt(2 Delta t) is standard
     # Brownian motion with dt = 2 Delta t
     assert W.paper_ball(dt_paper=0.01, paths_per_station=2).dt == pytest.approx(0.02)
+
+
+def test_discrete_walk_expectation_pins():
+    """The discrete walk's expectation for the paper's model (used by the GPU
+    experiment tests) tends to the Green solution as dt -> 0, and at the
+    paper's Delta t = 0.1 the oracle's own walks agree with it (and so show
+    the same two-thirds deficit against the Green solution)."""
+    import oracle
+    from paper_expectation import discrete_potential, green_potential
+    pr = W.paper_ball(dt_paper=1e-4)
+    x0 = W.paper_exp1_stations()[15]
+    assert abs(discrete_potential(pr, x0) / green_potential(pr, x0) - 1.0) < 2e-3
+    pr = W.paper_ball(dt_paper=0.1, paths_per_station=4000, stations=W.paper_exp1_stations()[::5])
+    stats, _, _ = oracle.solve(pr, 0)
+    for s, x in enumerate(pr.stations):
+        pred = discrete_potential(pr, x)
+        assert abs(stats[s]["mean"] - pred) < 4.0 * stats[s]["se"] + 1e-3 * abs(pred)
+    assert 0.6 < 1.0 - discrete_potential(pr, pr.stations[3]) / green_potential(pr, pr.stations[3]) < 0.72
