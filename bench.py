@@ -393,12 +393,12 @@ def tune_leg(reps=3):
     t_default = best()
     tuned = autotune.tune_batch(probs, kinds, walk_fraction=0.05)
     t_tuned = best()
-    F.fk_set_launch(W.PREC_MIXED_F64ACC, keep["block"], keep["blocks_per_cu"], keep["grab"])
+    F.fk_set_launch_dict(W.PREC_MIXED_F64ACC, keep)
     del ws
     torch.cuda.empty_cache()
     return {"default": {"seconds": t_default, "launch": keep},
-            "tuned": {"seconds": t_tuned, "launch": {k: tuned[k] for k in tuned if k != "tune_ms"},
-                      "tune_ms": tuned["tune_ms"]},
+            "tuned": {"seconds": t_tuned, "launch": {k: tuned[k] for k in F.LAUNCH_KEYS},
+                      "search": {k: tuned[k] for k in ("tune_ms", "default_ms", "walk_fraction", "trials")}},
             "tuned_over_default_time": t_tuned / t_default, "replays_each": reps}
 
 

@@ -369,14 +369,22 @@ fk_status fk_moving_average(const double *values, const double *se, int64_t n, i
  * wavefront takes from the global queue at once (1..64); adjoint_table: how
  * the adjoint gathers its occupation weights in LDS before they reach the
  * global counts -- 0: a dense per-station table when the grid has at most
- * 32768 voxels (512-thread blocks working through the stations one at a
- * time), else the hashed block table; 1: the hashed block table always.
- * Settings never change results. */
+ * 32768 voxels (1024-thread blocks working through the stations one at a
+ * time), else the hashed block table; 1: the hashed block table always;
+ * stripes: claim counters the task queue is split into, each a contiguous
+ * run of tasks that blocks b = s mod stripes start on (1..32; 0 = 8 for
+ * batches of problems with separate sources, 1 otherwise); refill_cost: the
+ * start-up cost R of a wavefront's walk refill, as 128 R macro-steps (a
+ * wavefront waits for k idle lanes, the smallest k with k (k + 1) >= 128 R
+ * times its walk-end rate per macro-step; 1..8192; 0 = 64).  Settings never
+ * change results. */
 typedef struct {
     int32_t block;
     int32_t blocks_per_cu;
     int32_t grab;
     int32_t adjoint_table;
+    int32_t stripes;
+    int32_t refill_cost;
 } fk_launch;
 
 fk_status fk_set_launch(int32_t precision, const fk_launch *launch);

@@ -6,9 +6,11 @@ the problem, installs the fastest setting for the problem's precision and
 records it in a JSON cache keyed by device name, precision, kind and the
 workload's shape (stations, walks per station, source kind, steps per walk
 order of magnitude).  ``apply_cached(problem, kind)`` installs a cached
-setting without timing anything.  ``tune_batch(problems, kinds)`` times the
-same candidates on a scaled-down copy of a whole batch (every problem with a
-fraction of its walks), so the choice reflects the batch's mix of problems.  The cache file is FKGRAV_TUNE_CACHE, or
+setting without timing anything.  ``tune_batch(problems, kinds)`` searches
+all launch settings (block size, blocks per CU, queue-run length, queue
+stripes, refill cost) one at a time on a scaled-down copy of a whole batch
+(every problem with a fraction of its walks), so the choice reflects the
+batch's mix of problems.  The cache file is FKGRAV_TUNE_CACHE, or
 ~/.cache/fkgrav_tune.json.  Settings never change results, only time.
 """
 from __future__ import annotations
@@ -54,7 +56,7 @@ def tune(prob, kind: int = 0, tuning_walks: int | None = None, force: bool = Fal
     key = _key(prob, kind)
     if key in cache and not force:
         s = cache[key]
-        F.fk_set_launch(prob.precision, s["block"], s["blocks_per_cu"], s["grab"])
+        F.fk_set_launch_dict(prob.precision, s)
         return s
     n = tuning_walks or max(2, min(prob.paths_per_station, 2048))
     small = prob.replace(paths_per_station=n)
@@ -72,39 +74,63 @@ def tune(prob, kind: int = 0, tuning_walks: int | None = None, force: bool = Fal
 def apply_cached(prob, kind: int = 0) -> dict | None:
     s = _load().get(_key(prob, kind))
     if s:
-        F.fk_set_launch(prob.precision, s["block"], s["blocks_per_cu"], s["grab"])
+        F.fk_set_launch_dict(prob.precision, s)
     return s
 
 
-BATCH_CANDIDATES = [(b, r, g) for b in (64, 128, 256) for r in (0, 2) for g in (16, 32, 64)]
+# Values tried for each launch setting of a batch (fk_launch), one setting at
+# a time from the current one (coordinate search): block size, resident blocks
+# per CU (0 = the occupancy limit), queue-run length, claim counters the queue
+# is split into (0 = the library's default for the batch), and the refill
+# rule's start-up cost (128 R; 0 = the default 64).
+BATCH_KNOBS = {"block": (64, 128, 256), "blocks_per_cu": (0, 2), "grab": (16, 32, 64),
+               "stripes": (0, 1, 4, 16), "refill_cost": (0, 16, 32, 128, 256)}
 
 
-def tune_batch(probs, kinds, walk_fraction: float = 0.05, min_walks: int = 64) -> dict:
-    """Times every candidate launch setting (block size, resident blocks per
-    CU -- 0 for the occupancy limit --, queue-run length) on the batch with
-    each problem's walks cut to walk_fraction, installs the fastest for the
-    batch's precision and returns it with its time.  Results never depend on
-    the setting."""
+def tune_batch(probs, kinds, walk_fraction: float = 0.05, min_walks: int = 64, rounds: int = 1,
+               repeats: int = 2) -> dict:
+    """Tunes the launch settings of a batch by coordinate search: starting
+    from the installed setting, each knob of BATCH_KNOBS in turn takes the
+    value with the shortest time (the best of `repeats` solves) with the
+    others fixed; `rounds` passes over the knobs.  Times are taken on the batch
+    with each problem's walks cut to walk_fraction.  Installs the result for
+    the batch's precision and returns it with its time and the default's.
+    Results never depend on the setting."""
     import torch
     small = [p.replace(paths_per_station=max(min_walks, int(p.paths_per_station * walk_fraction))) for p in probs]
     PB = F.PreparedBatch(small, kinds)
     ws = F.alloc_workspace(F.fk_batch_workspace_bytes(PB.problems))
     out = F.alloc_stats(PB.n_out)
     prec = probs[0].precision
-    best = None
-    for block, bpc, grab in BATCH_CANDIDATES:
-        F.fk_set_launch(prec, block, bpc, grab)
+
+    def timed(setting):
+        F.fk_set_launch_dict(prec, setting)
         F.fk_solve_batch(PB.problems, out, ws)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        F.fk_solve_batch(PB.problems, out, ws)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        if best is None or ms < best["tune_ms"]:
-            best = {"block": block, "blocks_per_cu": bpc, "grab": grab, "tune_ms": ms}
-    F.fk_set_launch(prec, best["block"], best["blocks_per_cu"], best["grab"])
-    best["walk_fraction"] = walk_fraction
+        best = None
+        for _ in range(repeats):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            F.fk_solve_batch(PB.problems, out, ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        return best
+
+    cur = F.fk_get_launch(prec)
+    cur_ms = default_ms = timed(cur)
+    trials = 1
+    for _ in range(rounds):
+        for knob, values in BATCH_KNOBS.items():
+            for v in values:
+                if v == cur[knob]:
+                    continue
+                cand = dict(cur, **{knob: v})
+                ms = timed(cand)
+                trials += 1
+                if ms < cur_ms:
+                    cur, cur_ms = cand, ms
+    F.fk_set_launch_dict(prec, cur)
     del ws
-    return best
+    return dict(cur, tune_ms=cur_ms, default_ms=default_ms, walk_fraction=walk_fraction, trials=trials)

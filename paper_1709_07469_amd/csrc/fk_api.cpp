@@ -66,7 +66,7 @@ bool timing_pair(std::pair<hipEvent_t, hipEvent_t>* out)
     *out = {a, b};
     return true;
 }
-fk_launch g_launch[3] = {{256, 0, 32, 0}, {256, 0, 32, 0}, {256, 0, 32, 0}};
+fk_launch g_launch[3] = {{256, 0, 32, 0, 0, 0}, {256, 0, 32, 0, 0, 0}, {256, 0, 32, 0, 0, 0}};
 
 int g_cus[64] = {0};
 
@@ -498,6 +498,10 @@ fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool b
     cfg->block = l.block;
     cfg->grid = (int)grid;
     cfg->grab = l.grab;
+    // claim counters: by default 8 (one run of tasks per XCD) for batches
+    // whose problems have separate sources, else one
+    cfg->stripes = l.stripes > 0 ? (uint32_t)l.stripes : (batch && !shared ? 8u : 1u);
+    cfg->refill_cost = l.refill_cost > 0 ? (uint32_t)l.refill_cost : 64u;
     return FK_OK;
 }
 
@@ -569,6 +573,8 @@ fk_status run_solve(int32_t kind, const double* stations, int64_t n_stations, co
         C.n_tasks = sl.t1 - sl.t0;
         C.grab = cfg.grab;
         C.total_waves = (uint32_t)((int64_t)cfg.grid * cfg.block / 64);
+        C.stripes = cfg.stripes;
+        C.refill_cost = cfg.refill_cost;
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
         const bool timed = timing && timing_begin(&ev, stream);
         if (p->precision == FK_F64) {
@@ -784,6 +790,8 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
         A.q0 = sl.q0;
         A.grab = cfg.grab;
         A.total_waves = (uint32_t)((int64_t)cfg.grid * cfg.block / 64);
+        A.stripes = cfg.stripes;
+        A.refill_cost = cfg.refill_cost;
         std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
         const bool timed = timing_begin(&ev, stream);
         le = fk::launch_batch_walk(A, cfg, stream, loop, shared);
@@ -879,6 +887,8 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
         cfg.block = fk::kAdjDenseBlock;
         cfg.grid = cus * bpc;
         cfg.grab = l.grab;
+        cfg.stripes = 1;
+        cfg.refill_cost = l.refill_cost > 0 ? (uint32_t)l.refill_cost : 64u;
     } else if ((st = plan_launch(p->precision, L.n_tasks, &cfg, false, loop_kind(p, nullptr), false, true)) != FK_OK) {
         return st;
     }
@@ -889,6 +899,8 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
     C.queue = reinterpret_cast<unsigned long long*>(ws + AL.queue);
     C.grab = cfg.grab;
     C.total_waves = (uint32_t)((int64_t)cfg.grid * cfg.block / 64);
+    C.stripes = cfg.stripes;
+    C.refill_cost = cfg.refill_cost;
     C.counts = counts;
     C.fwd_steps = reinterpret_cast<const uint32_t*>(static_cast<const char*>(fwd_workspace) + L.steps);
     C.nvox = AL.nvox;
@@ -1175,7 +1187,8 @@ fk_status fk_autotune(int32_t kind, const double* stations, int64_t n_stations, 
             for (int gi = 0; gi < 3 && st == FK_OK; ++gi) {
                 {
                     std::lock_guard<std::mutex> lk(g_mu);
-                    g_launch[precision] = fk_launch{blocks[bi], bpcs[pi], grabs[gi], keep.adjoint_table};
+                    g_launch[precision] = fk_launch{blocks[bi], bpcs[pi], grabs[gi], keep.adjoint_table, keep.stripes,
+                                                    keep.refill_cost};
                 }
                 float ms = 0.0f;
                 // one untimed run, then one timed run
@@ -1192,7 +1205,8 @@ fk_status fk_autotune(int32_t kind, const double* stations, int64_t n_stations, 
                 }
                 if (ms < best_t) {
                     best_t = ms;
-                    best_l = fk_launch{blocks[bi], bpcs[pi], grabs[gi], keep.adjoint_table};
+                    best_l = fk_launch{blocks[bi], bpcs[pi], grabs[gi], keep.adjoint_table, keep.stripes,
+                                       keep.refill_cost};
                 }
             }
         }
@@ -1278,6 +1292,8 @@ fk_status fk_set_launch(int32_t precision, const fk_launch* launch)
     if (launch->blocks_per_cu < 0 || launch->blocks_per_cu > 64) return fail(FK_EINVAL, "blocks_per_cu must lie in [0, 64]");
     if (launch->grab < 1 || launch->grab > 64) return fail(FK_EINVAL, "grab must lie in [1, 64]");
     if (launch->adjoint_table < 0 || launch->adjoint_table > 1) return fail(FK_EINVAL, "adjoint_table must be 0 or 1");
+    if (launch->stripes < 0 || launch->stripes > 32) return fail(FK_EINVAL, "stripes must lie in [0, 32]");
+    if (launch->refill_cost < 0 || launch->refill_cost > 8192) return fail(FK_EINVAL, "refill_cost must lie in [0, 8192]");
     std::lock_guard<std::mutex> lk(g_mu);
     g_launch[precision] = *launch;
 

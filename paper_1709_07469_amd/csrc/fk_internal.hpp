@@ -86,6 +86,8 @@ struct WalkCommon {
     int32_t exit_rule;
     int32_t grab;              // largest queue claim per wavefront
     uint32_t total_waves;      // resident wavefronts of the launch
+    uint32_t stripes;          // claim counters of the queue (1 .. 32)
+    uint32_t refill_cost;      // 128 x the start-up cost of the refill rule, in macro-steps
     int32_t domain;            // FK_DOMAIN_BOX / FK_DOMAIN_BALL
     double ctr[3];             // ball domain: centre, squared radius, radius
     double r2;
@@ -181,6 +183,8 @@ struct BatchArgs {
     int32_t grab;
     uint32_t total_waves;
     int32_t precision;
+    uint32_t stripes;
+    uint32_t refill_cost;
     int64_t chunk;
     // when every problem of the batch has the same source, that source (the
     // walk kernel then reads it from the kernel arguments, as a single
@@ -193,6 +197,8 @@ struct LaunchCfg {
     int block;
     int grid;
     int grab;
+    uint32_t stripes;
+    uint32_t refill_cost;
 };
 
 // Host launchers (one translation unit per kernel family).

@@ -43,20 +43,21 @@ namespace {
 
 constexpr int kMaxWaves = 4;        // 256 threads per block at most
 
-// In a batch of problems with separate sources the task queue is split into
-// kStripes contiguous stripes with a claim counter each (the queue slot of a
-// workspace holds 32 counters).  Block b starts on stripe b mod kStripes --
-// consecutive blocks are placed on the 8 XCDs in turn, so each XCD walks its
-// own contiguous range of tasks and its wavefronts hold walks of one problem
-// at a time (the problem-uniform fast path applies, and an XCD's L2 serves
-// one problem's grid) -- and a wavefront whose stripe runs out takes the
-// next.  Other launches keep one counter: their lanes share a source anyway,
-// and stripes that end on long walks lengthen the drain.
-constexpr uint32_t kStripes = 8;
+// The task queue can be split into contiguous stripes with a claim counter
+// each (the queue slot of a workspace holds kMaxStripes counters).  Block b
+// starts on stripe b mod stripes -- consecutive blocks are placed on the 8
+// XCDs in turn, so with 8 stripes each XCD walks its own contiguous range of
+// tasks and, in a batch of problems with separate sources, its wavefronts
+// hold walks of one problem at a time (the problem-uniform fast path applies,
+// and an XCD's L2 serves one problem's grid) -- and a wavefront whose stripe
+// runs out takes the next.  The launch settings choose the count: 8 for
+// batches of separate sources, 1 for other launches (their lanes share a
+// source anyway, and stripes that end on long walks lengthen the drain).
+constexpr uint32_t kMaxStripes = 32;
 
 __global__ void zero_queue_kernel(unsigned long long* q, uint32_t* status, uint32_t flags)
 {
-    if (threadIdx.x < kStripes) q[threadIdx.x] = 0ull;
+    if (threadIdx.x < kMaxStripes) q[threadIdx.x] = 0ull;
     if (status && threadIdx.x == 0) *status = flags;
 }
 
@@ -80,6 +81,8 @@ struct Queue {
     uint64_t n_tasks;
     uint32_t grab;
     uint32_t total_waves;
+    uint32_t stripes;              // 1 .. kMaxStripes
+    uint32_t refill_cost;          // 128 R of the refill rule below
 };
 
 struct Pool {
@@ -90,10 +93,9 @@ struct Pool {
     int64_t started;    // walks started after the first fill
 };
 
-template <uint32_t STRIPES>
 __device__ __forceinline__ Pool start_pool(const Queue& Q)
 {
-    return Pool{0ull, 0ull, Q.n_tasks, false, blockIdx.x % STRIPES, 0u, 0ull, -64};
+    return Pool{0ull, 0ull, Q.n_tasks, false, blockIdx.x % Q.stripes, 0u, 0ull, -64};
 }
 
 // Starting walks costs the wavefront about half a macro-step however many
@@ -103,14 +105,13 @@ __device__ __forceinline__ Pool start_pool(const Queue& Q)
 // + R/k macro-steps per walk (R = 1/2 the set-up), least for the smallest k
 // with k (k + 1) >= 128 R lambda.  lambda is the wavefront's own count of
 // walks started over its macro-steps so far: long walks (rare ends) refill
-// every lane at once, short ones wait for several.
-constexpr uint64_t kRefillCost128 = 64;   // 128 R (R = 1/4 measured the same)
+// every lane at once, short ones wait for several.  The launch settings give
+// 128 R (default 64: R = 1/2; R = 1/4 measured the same).
 
 // Refills idle lanes from the wavefront's claimed run, claiming a new run
 // from its stripe when it is empty (and moving to the next stripe when that
 // one is used up).  Returns the task of this lane if it was idle and got
 // one, else ~0.  Called by the whole wavefront once per macro-step.
-template <uint32_t STRIPES>
 __device__ __forceinline__ uint64_t refill(Pool& pool, const Queue& Q, bool active)
 {
     pool.rounds += 1;
@@ -119,12 +120,13 @@ __device__ __forceinline__ uint64_t refill(Pool& pool, const Queue& Q, bool acti
     const uint32_t n_idle = (uint32_t)__popcll(idle);
     // an all-idle wavefront always passes: started <= 64 rounds
     if (!pool.exhausted && pool.started > 0 &&
-        (uint64_t)n_idle * (n_idle + 1) * pool.rounds < kRefillCost128 * (uint64_t)pool.started)
+        (uint64_t)n_idle * (n_idle + 1) * pool.rounds < (uint64_t)Q.refill_cost * (uint64_t)pool.started)
         return ~0ull;
-    // each pass claims a run or uses up one stripe: STRIPES passes at most
-    for (uint32_t pass = 0; pass < STRIPES && pool.next == pool.end && !pool.exhausted; ++pass) {
-        const uint64_t lo = Q.n_tasks * pool.stripe / STRIPES;
-        const uint64_t hi = Q.n_tasks * (pool.stripe + 1) / STRIPES;
+    const uint32_t stripes = Q.stripes;
+    // each pass claims a run or uses up one stripe: stripes passes at most
+    for (uint32_t pass = 0; pass < stripes && pool.next == pool.end && !pool.exhausted; ++pass) {
+        const uint64_t lo = Q.n_tasks * pool.stripe / stripes;
+        const uint64_t hi = Q.n_tasks * (pool.stripe + 1) / stripes;
         uint64_t want = pool.left / (4ull * Q.total_waves);
         if (want < n_idle) want = n_idle;
         if (want > (uint64_t)Q.grab) want = (uint64_t)Q.grab;
@@ -134,11 +136,11 @@ __device__ __forceinline__ uint64_t refill(Pool& pool, const Queue& Q, bool acti
         if (old < hi - lo) {
             pool.next = lo + old;
             pool.end = lo + old + want < hi ? lo + old + want : hi;
-            pool.left = (hi - pool.end) * STRIPES;   // the whole queue's, estimated
-        } else if (STRIPES == 1 || ++pool.tried == STRIPES) {
+            pool.left = (hi - pool.end) * stripes;   // the whole queue's, estimated
+        } else if (stripes == 1 || ++pool.tried == stripes) {
             pool.exhausted = true;
         } else {
-            pool.stripe = (pool.stripe + 1) % STRIPES;
+            pool.stripe = (pool.stripe + 1) % stripes;
         }
     }
     const uint64_t avail = pool.end - pool.next;
@@ -803,7 +805,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
     Queue Q;
     LaneProblem<F64> P;
     if constexpr (BATCH) {
-        Q = Queue{A.queue, (uint64_t)A.n_tasks, (uint32_t)A.grab, A.total_waves};
+        Q = Queue{A.queue, (uint64_t)A.n_tasks, (uint32_t)A.grab, A.total_waves, A.stripes, A.refill_cost};
         P.C = nullptr;
         P.src = nullptr;
         P.sdt = T(0);
@@ -812,7 +814,8 @@ __device__ __forceinline__ void walk_body(const Args& A)
         P.key0 = P.key1 = P.pid = 0;
         P.max_steps = 0;
     } else {
-        Q = Queue{A.c.queue, (uint64_t)A.c.n_tasks, (uint32_t)A.c.grab, A.c.total_waves};
+        Q = Queue{A.c.queue, (uint64_t)A.c.n_tasks, (uint32_t)A.c.grab, A.c.total_waves, A.c.stripes,
+                  A.c.refill_cost};
         P.load(A.c, A.src);
         // held in vector registers, as a batch holds them: kept in scalar
         // registers beside the source's bodies they overflow the scalar file,
@@ -854,12 +857,11 @@ __device__ __forceinline__ void walk_body(const Args& A)
             f(source());
         }
     };
-    constexpr uint32_t STRIPES = (BATCH && !SHARED) ? kStripes : 1u;
     // drain rounds hold the first prism in registers (below); not in grid
     // loops, whose sources are mostly grids, nor in FP64 batches, whose
     // registers it costs more than it gains (both measured)
     constexpr bool kHeld = !loop_grid(LOOP) && !(F64 && BATCH);
-    Pool pool = start_pool<STRIPES>(Q);
+    Pool pool = start_pool(Q);
     Walker<F64, KAHAN, ADJ, LOOP, DENSE> W;
     W.active = false;
     W.rec = 0;
@@ -902,7 +904,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
     // The wavefront's walks until its queue is used up and they are done.
     auto run_waves = [&]() {
     for (;;) {
-        const uint64_t got = refill<STRIPES>(pool, Q, W.active);
+        const uint64_t got = refill(pool, Q, W.active);
         if (got != ~0ull) {
             const WalkCommon* Cp;
             uint64_t t;
@@ -1109,8 +1111,8 @@ __device__ __forceinline__ void walk_body(const Args& A)
         for (;;) {
             const int s = next_station;
             if (s < 0) break;
-            Q = Queue{A.c.queue + s, per, (uint32_t)A.c.grab, waves_per_station};
-            pool = start_pool<1>(Q);
+            Q = Queue{A.c.queue + s, per, (uint32_t)A.c.grab, waves_per_station, 1u, A.c.refill_cost};
+            pool = start_pool(Q);
             task_base = (uint64_t)s * per;
             run_waves();
             __syncthreads();    // the block's walks of station s are done

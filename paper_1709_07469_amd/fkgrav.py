@@ -71,7 +71,7 @@ class fk_stat(C.Structure):
 
 class fk_launch(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("grab", C.c_int32),
-                ("adjoint_table", C.c_int32)]
+                ("adjoint_table", C.c_int32), ("stripes", C.c_int32), ("refill_cost", C.c_int32)]
 
 
 class fk_problem(C.Structure):
@@ -306,14 +306,26 @@ def fk_moving_average(values, se=None, span: int = 5):
     return ov, oe
 
 
-def fk_set_launch(precision: int, block: int, blocks_per_cu: int = 0, grab: int = 32, adjoint_table: int = 0) -> None:
-    _check(lib().fk_set_launch(int(precision), C.byref(fk_launch(block, blocks_per_cu, grab, adjoint_table))))
+LAUNCH_KEYS = ("block", "blocks_per_cu", "grab", "adjoint_table", "stripes", "refill_cost")
+
+
+def fk_set_launch(precision: int, block: int, blocks_per_cu: int = 0, grab: int = 32, adjoint_table: int = 0,
+                  stripes: int = 0, refill_cost: int = 0) -> None:
+    _check(lib().fk_set_launch(int(precision), C.byref(fk_launch(block, blocks_per_cu, grab, adjoint_table, stripes,
+                                                                 refill_cost))))
+
+
+def fk_set_launch_dict(precision: int, d: dict) -> None:
+    """fk_set_launch from a dict of launch settings (missing keys: 0, the
+    defaults, except block 256 and grab 32)."""
+    fk_set_launch(precision, d.get("block", 256), d.get("blocks_per_cu", 0), d.get("grab", 32),
+                  d.get("adjoint_table", 0), d.get("stripes", 0), d.get("refill_cost", 0))
 
 
 def fk_get_launch(precision: int):
     l = fk_launch()
     _check(lib().fk_get_launch(int(precision), C.byref(l)))
-    return {"block": l.block, "blocks_per_cu": l.blocks_per_cu, "grab": l.grab, "adjoint_table": l.adjoint_table}
+    return {k: getattr(l, k) for k in LAUNCH_KEYS}
 
 
 def fk_timing_enable(on: bool) -> None:

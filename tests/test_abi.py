@@ -201,16 +201,19 @@ def test_workspace_layout_and_launch_settings():
     assert F.fk_workspace_bytes(0, 64, prm) == t
     old = F.fk_get_launch(0)
     F.fk_set_launch(0, 128, 2, 16)
-    assert F.fk_get_launch(0) == {"block": 128, "blocks_per_cu": 2, "grab": 16, "adjoint_table": 0}
-    F.fk_set_launch(0, 128, 2, 16, adjoint_table=1)
-    assert F.fk_get_launch(0)["adjoint_table"] == 1
-    with pytest.raises(F.FkError):
-        F.fk_set_launch(0, 128, 2, 16, adjoint_table=2)
+    assert F.fk_get_launch(0) == {"block": 128, "blocks_per_cu": 2, "grab": 16, "adjoint_table": 0, "stripes": 0,
+                                  "refill_cost": 0}
+    F.fk_set_launch(0, 128, 2, 16, adjoint_table=1, stripes=16, refill_cost=32)
+    got = F.fk_get_launch(0)
+    assert (got["adjoint_table"], got["stripes"], got["refill_cost"]) == (1, 16, 32)
+    for bad in ({"adjoint_table": 2}, {"stripes": 33}, {"stripes": -1}, {"refill_cost": 9000}):
+        with pytest.raises(F.FkError):
+            F.fk_set_launch(0, 128, 2, 16, **bad)
     with pytest.raises(F.FkError):
         F.fk_set_launch(0, 96)
     with pytest.raises(F.FkError):
         F.fk_set_launch(0, 512)
-    F.fk_set_launch(0, old["block"], old["blocks_per_cu"], old["grab"])
+    F.fk_set_launch_dict(0, old)
     assert F.fk_status_string(F.FK_EDOMAIN).startswith("station")
     assert F.fk_version() >= 100
 

@@ -46,12 +46,12 @@ class _table:
         from paper_1709_07469_amd import fkgrav as F
         self.keep = F.fk_get_launch(self.precision)
         k = self.keep
-        F.fk_set_launch(self.precision, k["block"], k["blocks_per_cu"], k["grab"], adjoint_table=self.table)
+        F.fk_set_launch_dict(self.precision, dict(k, adjoint_table=self.table))
 
     def __exit__(self, *exc):
         from paper_1709_07469_amd import fkgrav as F
         k = self.keep
-        F.fk_set_launch(self.precision, k["block"], k["blocks_per_cu"], k["grab"], adjoint_table=k["adjoint_table"])
+        F.fk_set_launch_dict(self.precision, k)
 
 
 @pytest.mark.parametrize("table", [0, 1])

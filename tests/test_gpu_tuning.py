@@ -38,7 +38,7 @@ def test_results_do_not_depend_on_launch_settings(precision):
                 else:
                     assert key == ref[kind], (block, bpc, grab, kind)
     finally:
-        F.fk_set_launch(precision, keep["block"], keep["blocks_per_cu"], keep["grab"])
+        F.fk_set_launch_dict(precision, keep)
 
 
 def test_autotuner_installs_and_caches_a_setting(tmp_path, monkeypatch):
@@ -62,7 +62,7 @@ def test_autotuner_installs_and_caches_a_setting(tmp_path, monkeypatch):
         again = autotune.apply_cached(pr, 0)
         assert again is not None and F.fk_get_launch(W.PREC_MIXED_F64ACC)["block"] == best["block"]
     finally:
-        F.fk_set_launch(W.PREC_MIXED_F64ACC, keep["block"], keep["blocks_per_cu"], keep["grab"])
+        F.fk_set_launch_dict(W.PREC_MIXED_F64ACC, keep)
 
 
 def test_batch_autotuner_picks_a_candidate_and_keeps_results():
@@ -76,11 +76,13 @@ def test_batch_autotuner_picks_a_candidate_and_keeps_results():
         before, _, _, _ = F.solve_batch(probs, kinds)
         best = autotune.tune_batch(probs, kinds, walk_fraction=0.25)
         say("  batch tuning picked", best)
-        assert (best["block"], best["blocks_per_cu"], best["grab"]) in autotune.BATCH_CANDIDATES
+        for knob, values in autotune.BATCH_KNOBS.items():
+            assert best[knob] in values or best[knob] == keep[knob], knob
+        assert best["tune_ms"] <= best["default_ms"]
         got = F.fk_get_launch(prec)
-        assert (got["block"], got["blocks_per_cu"], got["grab"]) == (best["block"], best["blocks_per_cu"], best["grab"])
+        assert all(got[k] == best[k] for k in F.LAUNCH_KEYS)
         after, _, _, _ = F.solve_batch(probs, kinds)
         for a, b in zip(before, after):
             assert a.tobytes() == b.tobytes()
     finally:
-        F.fk_set_launch(prec, keep["block"], keep["blocks_per_cu"], keep["grab"])
+        F.fk_set_launch_dict(prec, keep)
