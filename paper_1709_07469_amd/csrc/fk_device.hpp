@@ -261,13 +261,21 @@ __device__ __forceinline__ void normals_f64(const Block& b, const BmTables& T, d
     z1 = r * s;
 }
 
+// FP32 uniform in (0, 1] from the top 24 bits of a word: (k + 1) 2^-24 with
+// k = w >> 8, formed as k 2^-24 + 2^-24 in one fma (exact, like the product
+// of the integer k + 1 and 2^-24).
+__device__ __forceinline__ float uniform24(uint32_t w)
+{
+    return fmaf((float)(w >> 8), 0x1p-24f, 0x1p-24f);
+}
+
 // FP32 stream: two 24-bit uniforms in (0, 1] -> one Box-Muller pair, on the
 // hardware transcendental unit: v_log_f32 is log2, and v_sin_f32 / v_cos_f32
 // take their argument in revolutions, so sin(2 pi u) is one instruction.
 __device__ __forceinline__ void normals_f32(uint32_t wa, uint32_t wb, float& z0, float& z1)
 {
-    const float u1 = (float)((wa >> 8) + 1u) * 0x1p-24f;
-    const float u2 = (float)((wb >> 8) + 1u) * 0x1p-24f;
+    const float u1 = uniform24(wa);
+    const float u2 = uniform24(wb);
     const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));  // -2 ln 2 log2 u
     z0 = r * __builtin_amdgcn_cosf(u2);
     z1 = r * __builtin_amdgcn_sinf(u2);
@@ -323,7 +331,9 @@ __device__ __forceinline__ double bodies_f64(const SourceF64& s, double r, doubl
 // in flight at once: each floored coordinate t is clamped into [0, n-1] --
 // t lies in the grid exactly when the clamp leaves it unchanged (t is an
 // integer; a NaN never compares equal) -- and the load always reads a voxel
-// of the grid, its value dropped outside.  The host limits a grid to 2^31 - 1
+// of the grid, its value dropped outside.  A voxel value of -0 may come back
+// as -0 where the other paths give +0: no sum of densities can tell them apart
+// (the walk's sums start at +0).  The host limits a grid to 2^31 - 1
 // voxels, so the flat index fits 32 bits.
 // grid_in_* need a grid (has_grid); grid_* check for one.
 __device__ __forceinline__ double grid_in_f64(const SourceF64& s, double x, double y, double z)
@@ -337,7 +347,7 @@ __device__ __forceinline__ double grid_in_f64(const SourceF64& s, double x, doub
     const bool in = (cx == tx) & (cy == ty) & (cz == tz);
     const uint32_t v = ((uint32_t)cz * (uint32_t)s.n[1] + (uint32_t)cy) * (uint32_t)s.n[0] + (uint32_t)cx;
     const float r = s.rho[v];
-    return in ? 0.0 + (double)r : 0.0;
+    return in ? (double)r : 0.0;
 }
 
 __device__ __forceinline__ double grid_f64(const SourceF64& s, double x, double y, double z)
@@ -383,13 +393,14 @@ __device__ __forceinline__ float grid_in_f32(const SourceF32& s, float x, float 
     const float tx = floorf((x - s.origin[0]) * s.inv[0]);
     const float ty = floorf((y - s.origin[1]) * s.inv[1]);
     const float tz = floorf((z - s.origin[2]) * s.inv[2]);
-    const float cx = fminf(fmaxf(tx, 0.0f), s.nf[0] - 1.0f);
-    const float cy = fminf(fmaxf(ty, 0.0f), s.nf[1] - 1.0f);
-    const float cz = fminf(fmaxf(tz, 0.0f), s.nf[2] - 1.0f);
+    // the clamp into [0, n-1] as one median of three
+    const float cx = __builtin_amdgcn_fmed3f(tx, 0.0f, s.nf[0] - 1.0f);
+    const float cy = __builtin_amdgcn_fmed3f(ty, 0.0f, s.nf[1] - 1.0f);
+    const float cz = __builtin_amdgcn_fmed3f(tz, 0.0f, s.nf[2] - 1.0f);
     const bool in = (cx == tx) & (cy == ty) & (cz == tz);
     const uint32_t v = ((uint32_t)cz * (uint32_t)s.n[1] + (uint32_t)cy) * (uint32_t)s.n[0] + (uint32_t)cx;
     const float r = s.rho[v];
-    return in ? 0.0f + r : 0.0f;
+    return in ? r : 0.0f;
 }
 
 __device__ __forceinline__ float grid_f32(const SourceF32& s, float x, float y, float z)

@@ -389,7 +389,7 @@ struct Prec<false> {
     __device__ static T uniform(const Block& b, int j)
     {
         const uint32_t w = j == 0 ? b.w0 : j == 1 ? b.w1 : j == 2 ? b.w2 : b.w3;
-        return (float)((w >> 8) + 1u) * 0x1p-24f;
+        return uniform24(w);
     }
     __device__ static T sdt(const WalkCommon& C) { return C.sdt_f; }
 };
