@@ -473,7 +473,7 @@ int merge_loops(int a, int b)
 }
 
 fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false, int loop = 0,
-                      bool shared = false, bool adjoint = false)
+                      bool shared = false, bool adjoint = false, bool ukey = false)
 {
     fk_launch l;
     {
@@ -486,7 +486,7 @@ fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool b
     if (cus <= 0) return fail(FK_EDEVICE, "could not query the compute-unit count");
     int bpc = l.blocks_per_cu;
     if (bpc <= 0) {
-        const hipError_t oe = batch ? fk::batch_occupancy(precision, l.block, &bpc, loop, shared)
+        const hipError_t oe = batch ? fk::batch_occupancy(precision, l.block, &bpc, loop, shared, ukey)
                                     : fk::walk_occupancy(precision, l.block, &bpc, loop, adjoint);
         if (oe != hipSuccess || bpc <= 0)
             return fail(FK_EDEVICE, "occupancy query failed for block %d", l.block);
@@ -730,6 +730,14 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
             shared = std::memcmp(&o, &A.src32, sizeof o) == 0;
         }
     }
+    // one generator key for the whole batch (the usual case: the problems'
+    // streams differ by problem id): the walk kernel holds it in scalar
+    // registers
+    A.uniform_key = 1;
+    for (int32_t m = 1; m < n; ++m)
+        if (probs[m].params.seed != probs[0].params.seed) A.uniform_key = 0;
+    A.key0 = (uint32_t)(probs[0].params.seed & 0xffffffffull);
+    A.key1 = (uint32_t)(probs[0].params.seed >> 32);
 
     int64_t station_base = 0;
     auto* descs = reinterpret_cast<fk::BatchDesc*>(ws + BL.desc);
@@ -783,7 +791,7 @@ fk_status solve_batch(const fk_problem* probs, int32_t n, fk_stat* out, void* wo
         first = false;
         if (le != hipSuccess) return fail(FK_EDEVICE, "queue reset launch failed: %s", hipGetErrorString(le));
         fk::LaunchCfg cfg;
-        fk_status ps = plan_launch(precision, sl.t1 - sl.t0, &cfg, true, loop, shared);
+        fk_status ps = plan_launch(precision, sl.t1 - sl.t0, &cfg, true, loop, shared, false, A.uniform_key != 0);
         if (ps != FK_OK) return ps;
         A.task0 = sl.t0;
         A.n_tasks = sl.t1 - sl.t0;

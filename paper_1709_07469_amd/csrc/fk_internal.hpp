@@ -185,6 +185,9 @@ struct BatchArgs {
     int32_t precision;
     uint32_t stripes;
     uint32_t refill_cost;
+    // uniform_key: every problem's generator key is (key0, key1)
+    uint32_t key0, key1;
+    int32_t uniform_key;
     int64_t chunk;
     // when every problem of the batch has the same source, that source (the
     // walk kernel then reads it from the kernel arguments, as a single
@@ -239,6 +242,7 @@ hipError_t launch_write_words(uint64_t* dst, const uint64_t* host_words, int64_t
 hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, int loop, bool shared);
 hipError_t launch_batch_chunks(const BatchArgs& a, int64_t n_pairs, hipStream_t stream);
 hipError_t launch_batch_stations(const BatchArgs& a, int64_t n_stations, hipStream_t stream);
-hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, int loop = 0, bool shared = false);
+hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, int loop = 0, bool shared = false,
+                           bool ukey = false);
 
 }  // namespace fk

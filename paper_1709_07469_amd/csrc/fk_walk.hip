@@ -450,7 +450,9 @@ struct LaneProblem {
     uint32_t key0, key1, pid;
     int64_t max_steps;
 
-    __device__ __forceinline__ void load(const WalkCommon& c, const typename Prec<F64>::Src& s)
+    // keys = false leaves key0 and key1 as they are (a batch whose problems
+    // share the generator key holds it in scalar registers, set once).
+    __device__ __forceinline__ void load(const WalkCommon& c, const typename Prec<F64>::Src& s, bool keys = true)
     {
         C = &c;
         src = &s;
@@ -473,8 +475,10 @@ struct LaneProblem {
             hi1 = Prec<F64>::radius(c);
             hi2 = Prec<F64>::deep2(c);
         }
-        key0 = c.key0;
-        key1 = c.key1;
+        if (keys) {
+            key0 = c.key0;
+            key1 = c.key1;
+        }
         pid = c.problem_id;
         max_steps = c.max_steps;
     }
@@ -780,7 +784,9 @@ struct Walker {
 // their own claim counter; a block starts on station blockIdx mod S and,
 // when its station's tasks are all claimed and its walks done, flushes the
 // table and moves on to the next station with unclaimed tasks).
-template <bool F64, bool KAHAN, bool ADJ, bool BATCH, int LOOP, bool SHARED, bool DENSE, class Args>
+// UKEY (batches): every problem has the same generator key, passed in the
+// launch arguments, so the Philox key schedule is scalar work.
+template <bool F64, bool KAHAN, bool ADJ, bool BATCH, int LOOP, bool SHARED, bool DENSE, bool UKEY, class Args>
 __device__ __forceinline__ void walk_body(const Args& A)
 {
     using T = typename Prec<F64>::T;
@@ -812,6 +818,10 @@ __device__ __forceinline__ void walk_body(const Args& A)
         P.lo0 = P.lo1 = P.lo2 = P.hi0 = P.hi1 = P.hi2 = T(0);
         P.ball = false;
         P.key0 = P.key1 = P.pid = 0;
+        if constexpr (UKEY) {
+            P.key0 = A.key0;
+            P.key1 = A.key1;
+        }
         P.max_steps = 0;
     } else {
         Q = Queue{A.c.queue, (uint64_t)A.c.n_tasks, (uint32_t)A.c.grab, A.c.total_waves, A.c.stripes,
@@ -914,9 +924,9 @@ __device__ __forceinline__ void walk_body(const Args& A)
                 const BatchDesc& D = A.desc[m];
                 t = (uint64_t)(T - A.task_off[m]);
                 if constexpr (SHARED)
-                    P.load(D.c, shared_source<F64>(A));
+                    P.load(D.c, shared_source<F64>(A), !UKEY);
                 else
-                    P.load(D.c, SourceOf<F64>::get(D));
+                    P.load(D.c, SourceOf<F64>::get(D), !UKEY);
                 Cp = &D.c;
             } else {
                 t = task_base + got;
@@ -993,8 +1003,10 @@ __device__ __forceinline__ void walk_body(const Args& A)
                 const uint32_t ss = (uint32_t)__shfl((int)W.sctr, src);
                 uint32_t key0 = P.key0, key1 = P.key1, pid = P.pid;
                 if constexpr (BATCH) {
-                    key0 = (uint32_t)__shfl((int)P.key0, src);
-                    key1 = (uint32_t)__shfl((int)P.key1, src);
+                    if constexpr (!UKEY) {
+                        key0 = (uint32_t)__shfl((int)P.key0, src);
+                        key1 = (uint32_t)__shfl((int)P.key1, src);
+                    }
                     pid = (uint32_t)__shfl((int)P.pid, src);
                 }
                 if (r < B) {
@@ -1198,7 +1210,7 @@ __global__ void __launch_bounds__(256, ADJ                ? kAdjBlocksPerCu
                                                          : FK_F32_BLOCKS_PER_CU)
     walk_kernel(const typename std::conditional<F64, WalkArgsF64, WalkArgsF32>::type A)
 {
-    walk_body<F64, KAHAN, ADJ, false, LOOP, false, false>(A);
+    walk_body<F64, KAHAN, ADJ, false, LOOP, false, false, false>(A);
 }
 
 // The adjoint with dense station tables: one block of kAdjDenseBlock threads
@@ -1207,17 +1219,17 @@ template <bool F64, bool KAHAN, int LOOP>
 __global__ void __launch_bounds__(kAdjDenseBlock, 1)
     adjoint_dense_kernel(const typename std::conditional<F64, WalkArgsF64, WalkArgsF32>::type A)
 {
-    walk_body<F64, KAHAN, true, false, LOOP, false, true>(A);
+    walk_body<F64, KAHAN, true, false, LOOP, false, true, false>(A);
 }
 
-template <bool F64, bool KAHAN, int LOOP, bool SHARED>
+template <bool F64, bool KAHAN, int LOOP, bool SHARED, bool UKEY>
 __global__ void __launch_bounds__(256, loop_exit(LOOP)   ? 1
                                        : F64             ? FK_BATCH_F64_BLOCKS_PER_CU
                                        : (loop_grid(LOOP) && !SHARED) ? FK_BATCH_F32_GRID_BLOCKS_PER_CU
                                                                       : FK_BATCH_F32_BLOCKS_PER_CU)
     batch_walk_kernel(const BatchArgs A)
 {
-    walk_body<F64, KAHAN, false, true, LOOP, SHARED, false>(A);
+    walk_body<F64, KAHAN, false, true, LOOP, SHARED, false, UKEY>(A);
 }
 
 }  // namespace
@@ -1271,26 +1283,45 @@ const void* walk_fn(int precision, bool dense)
                                        : (const void*)walk_kernel<false, false, ADJ, LOOP>;
 }
 
-template <int LOOP, bool SHARED>
+// FP64 batches keep the per-lane key: their walks already fill the scalar
+// registers (the shared source's bodies, the FP64 bounds), and with the key
+// schedule there too they spill more and measured 9 % slower (grid batch).
+template <bool SHARED, bool UKEY>
+constexpr bool kF64Ukey = false;
+
+template <int LOOP, bool SHARED, bool UKEY>
 const void* batch_fn(int precision)
 {
-    return precision == FK_F64 ? (const void*)batch_walk_kernel<true, false, LOOP, SHARED>
-         : precision == FK_MIXED_KAHAN ? (const void*)batch_walk_kernel<false, true, LOOP, SHARED>
-                                       : (const void*)batch_walk_kernel<false, false, LOOP, SHARED>;
+    return precision == FK_F64 ? (const void*)batch_walk_kernel<true, false, LOOP, SHARED, kF64Ukey<SHARED, UKEY>>
+         : precision == FK_MIXED_KAHAN ? (const void*)batch_walk_kernel<false, true, LOOP, SHARED, UKEY>
+                                       : (const void*)batch_walk_kernel<false, false, LOOP, SHARED, UKEY>;
 }
 
-template <int LOOP, bool SHARED>
+template <int LOOP, bool SHARED, bool UKEY>
 void launch_batch(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream)
 {
     if (a.precision == FK_F64)
-        hipLaunchKernelGGL((batch_walk_kernel<true, false, LOOP, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0, stream,
-                           a);
+        hipLaunchKernelGGL((batch_walk_kernel<true, false, LOOP, SHARED, kF64Ukey<SHARED, UKEY>>), dim3(cfg.grid),
+                           dim3(cfg.block), 0, stream, a);
     else if (a.precision == FK_MIXED_KAHAN)
-        hipLaunchKernelGGL((batch_walk_kernel<false, true, LOOP, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0,
+        hipLaunchKernelGGL((batch_walk_kernel<false, true, LOOP, SHARED, UKEY>), dim3(cfg.grid), dim3(cfg.block), 0,
                            stream, a);
     else
-        hipLaunchKernelGGL((batch_walk_kernel<false, false, LOOP, SHARED>), dim3(cfg.grid), dim3(cfg.block), 0,
+        hipLaunchKernelGGL((batch_walk_kernel<false, false, LOOP, SHARED, UKEY>), dim3(cfg.grid), dim3(cfg.block), 0,
                            stream, a);
+}
+
+// Calls f with (shared source, uniform key) as compile-time constants.
+template <class F>
+void with_batch_mode(bool shared, bool ukey, F&& f)
+{
+    if (shared) {
+        if (ukey) f(std::true_type{}, std::true_type{});
+        else f(std::true_type{}, std::false_type{});
+    } else {
+        if (ukey) f(std::false_type{}, std::true_type{});
+        else f(std::false_type{}, std::false_type{});
+    }
 }
 
 // The loop variant of a single problem's launch (see loop_exit, loop_grid).
@@ -1343,19 +1374,20 @@ hipError_t walk_occupancy(int precision, int block, int* blocks_per_cu, int loop
 hipError_t launch_batch_walk(const BatchArgs& a, const LaunchCfg& cfg, hipStream_t stream, int loop, bool shared)
 {
     with_loop(loop, [&](auto L) {
-        if (shared)
-            launch_batch<decltype(L)::value, true>(a, cfg, stream);
-        else
-            launch_batch<decltype(L)::value, false>(a, cfg, stream);
+        with_batch_mode(shared, a.uniform_key != 0, [&](auto S, auto U) {
+            launch_batch<decltype(L)::value, decltype(S)::value, decltype(U)::value>(a, cfg, stream);
+        });
     });
     return hipGetLastError();
 }
 
-hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, int loop, bool shared)
+hipError_t batch_occupancy(int precision, int block, int* blocks_per_cu, int loop, bool shared, bool ukey)
 {
     const void* fn = nullptr;
     with_loop(loop, [&](auto L) {
-        fn = shared ? batch_fn<decltype(L)::value, true>(precision) : batch_fn<decltype(L)::value, false>(precision);
+        with_batch_mode(shared, ukey, [&](auto S, auto U) {
+            fn = batch_fn<decltype(L)::value, decltype(S)::value, decltype(U)::value>(precision);
+        });
     });
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, block, 0);
 }
