@@ -527,9 +527,11 @@ __device__ __forceinline__ double recip(double q)
 // atan(n / d) for finite n and d != 0.  With u = min(|n|, |d|) and
 // v = max(|n|, |d|), t = u / v lies in [0, 1]; c = k/64 is a grid point near
 // t (k from the reciprocal estimate, any k with |t - c| <= 1/128 + 1e-9 does)
-// and atan t = atan c + atan(delta) with delta = (u - c v)/(v + c u), one
-// division, its series to delta^9 (truncation below 1e-24); pi/2 - atan t
-// when |n| > |d|, and the sign of n/d.  No branches.
+// and atan t = atan c + atan(delta) with delta = (u - c v)/(v + c u) (the
+// quotient from the refined reciprocal of its positive denominator and one
+// residual correction, within about an ulp), its series to delta^9
+// (truncation below 1e-24); pi/2 - atan t when |n| > |d|, and the sign of
+// n/d.  No branches.
 __device__ __forceinline__ double atan_q(double n, double d, const AtanTable& A)
 {
     const double an = fabs(n), ad = fabs(d);
@@ -538,7 +540,10 @@ __device__ __forceinline__ double atan_q(double n, double d, const AtanTable& A)
     double k = __builtin_rint(u * __builtin_amdgcn_rcp(v) * (double)AtanTable::kN);
     k = fmin(fmax(k, 0.0), (double)AtanTable::kN);
     const double c = k * (1.0 / AtanTable::kN);
-    const double dl = fma(-c, v, u) / fma(c, u, v);
+    const double num = fma(-c, v, u), den = fma(c, u, v);
+    const double rd = recip(den);
+    double dl = num * rd;
+    dl = fma(fma(-den, dl, num), rd, dl);
     const double z = dl * dl;
     double p = fma(z, 0x1.c71c71c71c71cp-4, -0x1.2492492492492p-3);   // 1/9, -1/7
     p = fma(p, z, 0x1.999999999999ap-3);                                // 1/5
@@ -608,7 +613,9 @@ __device__ __forceinline__ double edge_terms(double u, double v, double wl, doub
 // number of upper coordinates (Nagy, Papp & Benedek 2000); a term whose
 // prefactor is zero vanishes.  The corners are taken in pairs along each of
 // the 12 edges, each edge carrying the two terms whose prefactors stay fixed
-// along it (edge_terms): 8 square roots, 12 logarithms and 12 arctangents
+// along it (edge_terms): 8 square roots (sqrt_nonneg, from the hardware
+// reciprocal square root: a corner distance is zero or far above the
+// subnormal range), 12 logarithms and 12 arctangents
 // instead of 24 of each, and no cancellation between the two corners' large
 // logarithms and angles.  Every term is evaluated and the vanishing ones
 // selected away (their logarithm or quotient may be infinite), so the lanes
@@ -629,7 +636,7 @@ __device__ inline double prism_newton(const double* q, double px, double py, dou
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int k = 0; k < 2; ++k) r[i][j][k] = sqrt(X2[i] + Y2[j] + Z2[k]);
+            for (int k = 0; k < 2; ++k) r[i][j][k] = sqrt_nonneg(X2[i] + Y2[j] + Z2[k]);
     double v = 0.0;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
