@@ -71,12 +71,19 @@ ALGO_BYTES_PER_WALK = 36
 # VALU: SQ_INSTS_VALU per Brownian step in lane-instructions (x 64),
 # SQ_ACTIVE_INST_VALU x 4 cycles over the SIMD-cycles the kernel ran
 # (GRBM_GUI_ACTIVE x 4 SIMDs x 256 CUs / 8 XCDs summed; clamped at 1), and
-# the FLOP counts (ADD + MUL + 2 FMA + TRANS, F64 and F32) per step.  Bytes:
+# the FLOP counts (ADD + MUL + 2 FMA + TRANS, F64 and F32) per step, the L2
+# hit rate (TCC_HIT / (TCC_HIT + TCC_MISS)).  Bytes:
 # FETCH_SIZE and WRITE_SIZE per launch, each scaled by what the counter reads
 # for a device copy of known size.  Figures are reported only while the
 # sources still hash to the recorded value.
 COUNTERS = {
-    "sources_sha256": None,
+    "sources_sha256": "a372b54c8352c18b306eef9e77c882e48a784686e5f2d18267c6f96948c004e2",
+    "cfg4_mixed": {"valu_lane_instr_per_step": 110.58825, "valu_busy": 1.103242, "fp64_flop_per_step": 2.104392, "fp32_flop_per_step": 30.680143, "fetch_kib": 991308.703125, "write_kib": 80740224.023438, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.998216},
+    "cfg4_f64": {"valu_lane_instr_per_step": 273.045588, "valu_busy": 0.939628, "fp64_flop_per_step": 143.526899, "fp32_flop_per_step": 0.06131, "fetch_kib": 802429.34375, "write_kib": 74558999.585938, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.998727},
+    "cfg2_f64": {"valu_lane_instr_per_step": 222.112118, "valu_busy": 0.980785, "fp64_flop_per_step": 108.152378, "fp32_flop_per_step": 0.073811, "fetch_kib": 169.46875, "write_kib": 875512.328125, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.874837},
+    "cfg2_mixed": {"valu_lane_instr_per_step": 84.679978, "valu_busy": 1.044448, "fp64_flop_per_step": 2.193898, "fp32_flop_per_step": 23.572416, "fetch_kib": 7850.09375, "write_kib": 1076011.984375, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.973772},
+    "cfg3_f64": {"valu_lane_instr_per_step": 268.136761, "valu_busy": 0.944927, "fp64_flop_per_step": 117.714208, "fp32_flop_per_step": 0.094086, "fetch_kib": 530431902.354167, "write_kib": 17314637.635417, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.86657},
+    "cfg3_mixed": {"valu_lane_instr_per_step": 114.446908, "valu_busy": 0.697574, "fp64_flop_per_step": 2.165511, "fp32_flop_per_step": 31.388643, "fetch_kib": 478230026.3125, "write_kib": 16339438.395833, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.879957},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp", "paper_1709_07469_amd/csrc/fk_stats.hpp",
@@ -123,7 +130,8 @@ def roofline(key, precision, steps_per_launch, kernel_ms, walks_per_launch, grid
                 "valu_issue_frac": rec["valu_lane_instr_per_step"] * rate / PEAK_LANE_OPS,
                 "fp64_flop_per_step": rec["fp64_flop_per_step"], "fp32_flop_per_step": rec["fp32_flop_per_step"],
                 "fp64_frac_of_peak": rec["fp64_flop_per_step"] * rate / PEAK_F64_FLOPS,
-                "fp32_frac_of_peak": rec["fp32_flop_per_step"] * rate / PEAK_F32_FLOPS}
+                "fp32_frac_of_peak": rec["fp32_flop_per_step"] * rate / PEAK_F32_FLOPS,
+                "l2_hit": rec.get("l2_hit")}
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic,
             "kernel_avg_ms": kernel_ms, "steps_per_launch": steps_per_launch,
