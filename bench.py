@@ -350,9 +350,12 @@ def cfg3_leg(reps=2):
     from paper_1709_07469_amd import workloads as W
     tg = load_targets()["cfg3"]
     out = {"workload": "[-1,1]^3, 128^3 FP32 grid of 5 prisms (log-normal contrasts), exact prism data, "
-                       "16x16 stations at z = 0.5, 1e6 walks/station, dt = 1e-3, potential"}
-    for name, prec in (("f64", W.PREC_F64), ("mixed", W.PREC_MIXED_F64ACC)):
-        prob = W.cfg3(precision=prec)
+                       "16x16 stations at z = 0.5, 1e6 walks/station, dt = 1e-3, potential; *_levels: the same "
+                       "grid given by levels (a byte per voxel and its 6 densities)"}
+    stats = {}
+    for name, prec, levels in (("f64", W.PREC_F64, False), ("mixed", W.PREC_MIXED_F64ACC, False),
+                               ("f64_levels", W.PREC_F64, True), ("mixed_levels", W.PREC_MIXED_F64ACC, True)):
+        prob = W.cfg3(precision=prec).replace(grid_levels=levels)
         P = F.Prepared(prob)
         ws = F.alloc_workspace(F.fk_workspace_bytes(0, prob.n_stations, P.params))
         o = F.alloc_stats(prob.n_stations)
@@ -362,15 +365,21 @@ def cfg3_leg(reps=2):
         solve()
         kms, launches, ems = walk_kernel_ms(solve, reps)
         st = F.stats_to_numpy(o)[:prob.n_stations]
+        stats[name] = st
         steps = int(st["sum_steps"].sum())
+        prec_name = name.split("_")[0]
+        grid_bytes = prob.rho.size * (1 if levels else 4)
         out[name] = {"value": steps / (ems * 1e-3), "unit": "Brownian steps/s", "seconds_per_solve": ems / 1e3,
                      "walk_kernel_share": kms * launches / ems,
-                     "roofline": roofline("cfg3_" + name, name, steps / launches, kms,
-                                          prob.n_stations * prob.paths_per_station, prob.rho.nbytes),
+                     "roofline": roofline("cfg3_" + name, prec_name, steps / launches, kms,
+                                          prob.n_stations * prob.paths_per_station, grid_bytes),
                      "vs_closed_form": closed_form_error(st["mean"], st["se"], tg["u"])}
+        if levels:
+            out[name]["bitwise_equal_to_fp32_grid"] = stats[prec_name].tobytes() == st.tobytes()
         del ws
         torch.cuda.empty_cache()
     out["mixed_speedup"] = out["mixed"]["value"] / out["f64"]["value"]
+    out["levels_speedup"] = {p: out[p + "_levels"]["value"] / out[p]["value"] for p in ("f64", "mixed")}
     return out
 
 

@@ -124,7 +124,13 @@ typedef struct {
 /* Density rho(x) (paper eq. 4), the sum of
  *   - a voxel grid: rho (DEVICE, float, [n[2]][n[1]][n[0]], x fastest; NULL
  *     for none); voxel (i,j,k) is [origin + (i,j,k)*spacing, origin +
- *     (i+1,j+1,k+1)*spacing), zero outside the grid;
+ *     (i+1,j+1,k+1)*spacing), zero outside the grid.  Or the same grid given
+ *     by levels: rho_index (DEVICE, uint8, the same layout) selects the
+ *     voxel's density rho_levels[rho_index] (DEVICE, 256 floats: any byte
+ *     indexes inside it; entries no voxel selects are never read), with rho
+ *     NULL.  A model of at most 256 distinct densities (a few units, each
+ *     of one density) then takes a quarter of the memory and cache of the
+ *     FP32 grid; the densities, so the results, are the same;
  *   - analytic homogeneous prisms (HOST, n_prisms rows lo[3], hi[3], rho),
  *     half-open [lo, hi) per axis;
  *   - analytic homogeneous balls (HOST, n_spheres rows c[3], radius, rho),
@@ -141,6 +147,8 @@ typedef struct {
     const double *spheres;
     int32_t n_spheres;
     int32_t pad2;
+    const uint8_t *rho_index;
+    const float *rho_levels;
 } fk_source;
 
 /* Dirichlet data g (paper eq. 1).  For FK_BC_FACE_GRID, data is DEVICE memory

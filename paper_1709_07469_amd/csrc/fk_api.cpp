@@ -281,7 +281,9 @@ double dist2(const double x[3], const double c[3])
 fk_status check_source(const fk_source* s)
 {
     if (!s) return fail(FK_EINVAL, "source is NULL");
-    if (s->rho) {
+    if (s->rho && s->rho_index) return fail(FK_EINVAL, "give the grid as rho or as rho_index, not both");
+    if (s->rho_index && !s->rho_levels) return fail(FK_EINVAL, "rho_levels is NULL (rho_index needs 256 levels)");
+    if (s->rho || s->rho_index) {
         int64_t nv = 1;
         for (int c = 0; c < 3; ++c) {
             if (s->n[c] < 1) return fail(FK_EINVAL, "grid size n[%d] must be >= 1", c);
@@ -419,15 +421,21 @@ void fill_bc(fk::BoundaryArgs& B, const fk_boundary* bc)
     }
 }
 
+// Whether the source has a voxel grid (as FP32 densities or by levels).
+bool has_grid(const fk_source* s) { return s && (s->rho || s->rho_index); }
+
 void fill_source_f64(fk::SourceF64& S, const fk_source* s)
 {
     std::memset(&S, 0, sizeof S);
+    const bool grid = has_grid(s);
     S.rho = s->rho;
-    S.has_grid = s->rho != nullptr;
+    S.idx = s->rho_index;
+    S.levels = s->rho_index ? s->rho_levels : nullptr;
+    S.has_grid = grid;
     for (int c = 0; c < 3; ++c) {
-        S.n[c] = s->rho ? s->n[c] : 0;
+        S.n[c] = grid ? s->n[c] : 0;
         S.origin[c] = s->origin[c];
-        S.spacing[c] = s->rho ? s->spacing[c] : 1.0;
+        S.spacing[c] = grid ? s->spacing[c] : 1.0;
         S.inv[c] = 1.0 / S.spacing[c];
         S.exact[c] = power_of_two(S.spacing[c]);
     }
@@ -442,13 +450,16 @@ void fill_source_f64(fk::SourceF64& S, const fk_source* s)
 void fill_source_f32(fk::SourceF32& S, const fk_source* s)
 {
     std::memset(&S, 0, sizeof S);
+    const bool grid = has_grid(s);
     S.rho = s->rho;
-    S.has_grid = s->rho != nullptr;
+    S.idx = s->rho_index;
+    S.levels = s->rho_index ? s->rho_levels : nullptr;
+    S.has_grid = grid;
     for (int c = 0; c < 3; ++c) {
-        S.n[c] = s->rho ? s->n[c] : 0;
+        S.n[c] = grid ? s->n[c] : 0;
         S.nf[c] = (float)S.n[c];
         S.origin[c] = (float)s->origin[c];
-        S.inv[c] = s->rho ? (float)(1.0 / s->spacing[c]) : 1.0f;
+        S.inv[c] = grid ? (float)(1.0 / s->spacing[c]) : 1.0f;
     }
     S.n_prisms = s->n_prisms;
     S.n_spheres = s->n_spheres;
@@ -460,16 +471,18 @@ void fill_source_f32(fk::SourceF32& S, const fk_source* s)
 
 // The stepping loop a problem needs: 0 box, 1 ball exit test, 2 bridge test;
 // plus 4 when its source has a voxel grid (the loop then loads grid values
-// ahead).  A batch takes the most general exit test and the grid bit of any.
+// ahead), and 8 more when that grid is given by levels.  A batch takes the
+// most general exit test and the grid bits of any (its grids must all be of
+// one kind, which check_batch ensures).
 int loop_kind(const fk_params* p, const fk_source* s)
 {
     const int e = p->exit_rule == FK_EXIT_BRIDGE ? 2 : p->domain == FK_DOMAIN_BALL ? 1 : 0;
-    return e | (s && s->rho ? 4 : 0);
+    return e | (has_grid(s) ? 4 : 0) | (s && s->rho_index ? 8 : 0);
 }
 
 int merge_loops(int a, int b)
 {
-    return std::max(a & 3, b & 3) | ((a | b) & 4);
+    return std::max(a & 3, b & 3) | ((a | b) & 12);
 }
 
 fk_status plan_launch(int precision, int64_t n_tasks, fk::LaunchCfg* cfg, bool batch = false, int loop = 0,
@@ -637,6 +650,7 @@ fk_status check_batch(const fk_problem* probs, int32_t n)
     if (n > 0 && !probs) return fail(FK_EINVAL, "problems is NULL");
     fk_status st;
     int64_t pairs = 0;
+    int levels_grid = 0;   // 1: the grids seen so far are given by levels, -1: FP32, 0: none yet
     for (int32_t m = 0; m < n; ++m) {
         const fk_problem& P = probs[m];
         if ((st = check_params(P.kind, P.n_stations, &P.params)) != FK_OK) return st;
@@ -650,6 +664,13 @@ fk_status check_batch(const fk_problem* probs, int32_t n)
             return fail(FK_EINVAL, "problem %d: all problems of a batch need the same precision", m);
         if (P.params.slice_walks != probs[0].params.slice_walks)
             return fail(FK_EINVAL, "problem %d: all problems of a batch need the same slice_walks", m);
+        // one kernel instance looks the grids up: all FP32 or all by levels
+        if (P.source.rho_index && levels_grid < 0) return fail(FK_EINVAL, "problem %d: a batch's grids must all be "
+                                                               "FP32 densities or all given by levels", m);
+        if (P.source.rho && levels_grid > 0) return fail(FK_EINVAL, "problem %d: a batch's grids must all be "
+                                                        "FP32 densities or all given by levels", m);
+        if (P.source.rho_index) levels_grid = 1;
+        else if (P.source.rho) levels_grid = -1;
         pairs += P.n_stations * ((P.params.paths_per_station + kChunk - 1) / kChunk);
         if (pairs > (1ll << 31) - 1) return fail(FK_EUNSUPPORTED, "a batch must have fewer than 2^31 (station, chunk) pairs");
     }
@@ -856,7 +877,7 @@ fk_status adjoint(int32_t kind, const double* stations, int64_t n_stations, cons
     if ((st = check_source(src)) != FK_OK) return st;
     if ((st = check_bc(bc)) != FK_OK) return st;
     if ((st = check_domain(box, p, bc)) != FK_OK) return st;
-    if (!src->rho) return fail(FK_EINVAL, "the adjoint needs a voxel grid (source.rho is NULL)");
+    if (!has_grid(src)) return fail(FK_EINVAL, "the adjoint needs a voxel grid (source.rho and rho_index are NULL)");
     if (p->slice_walks != 0)
         return fail(FK_EINVAL, "the adjoint replays a record-mode forward solve (slice_walks must be 0)");
     if (!grad_rho) return fail(FK_EINVAL, "grad_rho is NULL");
@@ -1022,7 +1043,7 @@ fk_status fk_solve_static(int32_t kind, const double* stations, int64_t n_statio
 
 size_t fk_adjoint_workspace_bytes(int64_t n_stations, const fk_source* source)
 {
-    if (n_stations < 0 || !source || check_source(source) != FK_OK || !source->rho) return 0;
+    if (n_stations < 0 || !source || check_source(source) != FK_OK || !has_grid(source)) return 0;
     return make_adj_layout(n_stations, source).total;
 }
 

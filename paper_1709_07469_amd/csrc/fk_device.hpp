@@ -334,8 +334,11 @@ __device__ __forceinline__ double bodies_f64(const SourceF64& s, double r, doubl
 // of the grid, its value dropped outside.  A voxel value of -0 may come back
 // as -0 where the other paths give +0: no sum of densities can tell them apart
 // (the walk's sums start at +0).  The host limits a grid to 2^31 - 1
-// voxels, so the flat index fits 32 bits.
+// voxels, so the flat index fits 32 bits.  LEVELS: the grid is given by
+// levels, the voxel's density levels[idx[v]] (two dependent loads; the index
+// grid is a quarter of the FP32 grid's size).
 // grid_in_* need a grid (has_grid); grid_* check for one.
+template <bool LEVELS = false>
 __device__ __forceinline__ double grid_in_f64(const SourceF64& s, double x, double y, double z)
 {
     const double tx = grid_axis_f64(x, s.origin[0], s.spacing[0], s.inv[0], s.exact[0]);
@@ -346,18 +349,22 @@ __device__ __forceinline__ double grid_in_f64(const SourceF64& s, double x, doub
     const double cz = fmin(fmax(tz, 0.0), (double)(s.n[2] - 1));
     const bool in = (cx == tx) & (cy == ty) & (cz == tz);
     const uint32_t v = ((uint32_t)cz * (uint32_t)s.n[1] + (uint32_t)cy) * (uint32_t)s.n[0] + (uint32_t)cx;
-    const float r = s.rho[v];
+    const float r = LEVELS ? s.levels[s.idx[v]] : s.rho[v];
     return in ? (double)r : 0.0;
 }
 
+// LEVELS: the kernel's grids are given by levels (a compile-time property
+// of the launch, like the stepping loop's lookup).
+template <bool LEVELS = false>
 __device__ __forceinline__ double grid_f64(const SourceF64& s, double x, double y, double z)
 {
-    return s.has_grid ? grid_in_f64(s, x, y, z) : 0.0;
+    return s.has_grid ? grid_in_f64<LEVELS>(s, x, y, z) : 0.0;
 }
 
+template <bool LEVELS = false>
 __device__ __forceinline__ double rho_f64(const SourceF64& s, double x, double y, double z)
 {
-    return bodies_f64(s, grid_f64(s, x, y, z), x, y, z);
+    return bodies_f64(s, grid_f64<LEVELS>(s, x, y, z), x, y, z);
 }
 
 __device__ __forceinline__ int voxel_f32(const SourceF32& s, float x, float y, float z)
@@ -388,6 +395,7 @@ __device__ __forceinline__ float bodies_f32(const SourceF32& s, float r, float x
 
 // FP32 stepping's grid lookup, branch-free like grid_f64 (the same voxel as
 // voxel_f32).
+template <bool LEVELS = false>
 __device__ __forceinline__ float grid_in_f32(const SourceF32& s, float x, float y, float z)
 {
     const float tx = floorf((x - s.origin[0]) * s.inv[0]);
@@ -399,18 +407,20 @@ __device__ __forceinline__ float grid_in_f32(const SourceF32& s, float x, float 
     const float cz = __builtin_amdgcn_fmed3f(tz, 0.0f, s.nf[2] - 1.0f);
     const bool in = (cx == tx) & (cy == ty) & (cz == tz);
     const uint32_t v = ((uint32_t)cz * (uint32_t)s.n[1] + (uint32_t)cy) * (uint32_t)s.n[0] + (uint32_t)cx;
-    const float r = s.rho[v];
+    const float r = LEVELS ? s.levels[s.idx[v]] : s.rho[v];
     return in ? r : 0.0f;
 }
 
+template <bool LEVELS = false>
 __device__ __forceinline__ float grid_f32(const SourceF32& s, float x, float y, float z)
 {
-    return s.has_grid ? grid_in_f32(s, x, y, z) : 0.0f;
+    return s.has_grid ? grid_in_f32<LEVELS>(s, x, y, z) : 0.0f;
 }
 
+template <bool LEVELS = false>
 __device__ __forceinline__ float rho_f32(const SourceF32& s, float x, float y, float z)
 {
-    return bodies_f32(s, grid_f32(s, x, y, z), x, y, z);
+    return bodies_f32(s, grid_f32<LEVELS>(s, x, y, z), x, y, z);
 }
 
 // ---------------------------------------------------------------------------

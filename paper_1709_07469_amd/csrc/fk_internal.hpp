@@ -14,6 +14,8 @@ namespace fk {
 
 struct SourceF64 {
     const float* rho;          // device voxel grid or nullptr
+    const uint8_t* idx;        // or the grid by levels: device index grid
+    const float* levels;       // and its 256 densities
     int32_t n[3];
     int32_t has_grid;
     double origin[3];
@@ -29,6 +31,8 @@ struct SourceF64 {
 
 struct SourceF32 {
     const float* rho;
+    const uint8_t* idx;
+    const float* levels;
     int32_t n[3];
     int32_t has_grid;
     float origin[3];

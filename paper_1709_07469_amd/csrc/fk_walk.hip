@@ -342,8 +342,10 @@ struct Prec<true> {
     static constexpr int kMacro = 2;     // steps per 3 blocks
     __device__ static void normals(const Block& b, T* z, const BmTables* t) { normals_f64(b, *t, z[0], z[1]); }
     __device__ static T fmat(T a, T b, T c) { return fma(a, b, c); }
-    __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f64(s, x, y, z); }
-    __device__ static T grid_in(const Src& s, T x, T y, T z) { return grid_in_f64(s, x, y, z); }
+    template <bool LEVELS>
+    __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f64<LEVELS>(s, x, y, z); }
+    template <bool LEVELS>
+    __device__ static T grid_in(const Src& s, T x, T y, T z) { return grid_in_f64<LEVELS>(s, x, y, z); }
     __device__ static T bodies(const Src& s, T g, T x, T y, T z, int j0 = 0) { return bodies_f64(s, g, x, y, z, j0); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f64(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo[c]; }
@@ -374,8 +376,10 @@ struct Prec<false> {
         normals_f32(b.w2, b.w3, z[2], z[3]);
     }
     __device__ static T fmat(T a, T b, T c) { return fmaf(a, b, c); }
-    __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f32(s, x, y, z); }
-    __device__ static T grid_in(const Src& s, T x, T y, T z) { return grid_in_f32(s, x, y, z); }
+    template <bool LEVELS>
+    __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f32<LEVELS>(s, x, y, z); }
+    template <bool LEVELS>
+    __device__ static T grid_in(const Src& s, T x, T y, T z) { return grid_in_f32<LEVELS>(s, x, y, z); }
     __device__ static T bodies(const Src& s, T g, T x, T y, T z, int j0 = 0) { return bodies_f32(s, g, x, y, z, j0); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f32(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo_f[c]; }
@@ -487,11 +491,14 @@ struct LaneProblem {
 // The stepping loop a kernel instance is built for.  Bits 0-1: 0 = the box
 // domain's loop with the step-end exit test only; 1 = with the ball domain's
 // exit test; 2 = also with the Brownian-bridge test.  Bit 2: the density
-// source has a voxel grid, whose values each macro-step loads ahead.  A launch
-// uses the least general loop its problems need.
+// source has a voxel grid, whose values each macro-step loads ahead; bit 3
+// (with bit 2): the grids are given by levels (an index grid and its
+// densities).  A launch uses the least general loop its problems need.
 constexpr int kLoopGrid = 4;
+constexpr int kLoopLevels = 8;
 constexpr int loop_exit(int loop) { return loop & 3; }
 constexpr bool loop_grid(int loop) { return (loop & kLoopGrid) != 0; }
+constexpr bool loop_levels(int loop) { return (loop & kLoopLevels) != 0; }
 
 // One lane's walk.
 template <bool F64, bool KAHAN, bool ADJ, int LOOP, bool DENSE = false>
@@ -573,7 +580,8 @@ struct Walker {
         // source is checked, once for all the macro-step's loads.
         if (!ADJ && loop_grid(LOOP) && src.has_grid) {
 #pragma unroll
-            for (int s = 0; s < MACRO; ++s) g[s] = Prec<F64>::grid_in(src, z[3 * s], z[3 * s + 1], z[3 * s + 2]);
+            for (int s = 0; s < MACRO; ++s)
+                g[s] = Prec<F64>::template grid_in<loop_levels(LOOP)>(src, z[3 * s], z[3 * s + 1], z[3 * s + 2]);
         }
     }
 
@@ -963,7 +971,7 @@ __device__ __forceinline__ void walk_body(const Args& A)
                     W.sc.sign = ti.w ? -1 : 1;
                     W.sc.add(Prec<F64>::voxel(source(), W.x0, W.x1, W.x2), 1);
                 } else {
-                    W.rp = Prec<F64>::rho(source(), W.x0, W.x1, W.x2);
+                    W.rp = Prec<F64>::template rho<loop_levels(LOOP)>(source(), W.x0, W.x1, W.x2);
                 }
                 W.deep = false;
                 if (loop_exit(LOOP) == 2 && P.bridge) {
@@ -1254,6 +1262,9 @@ template <class F>
 void with_loop(int loop, F&& f)
 {
     switch (loop) {
+    case 14: f(std::integral_constant<int, 14>{}); break;
+    case 13: f(std::integral_constant<int, 13>{}); break;
+    case 12: f(std::integral_constant<int, 12>{}); break;
     case 6: f(std::integral_constant<int, 6>{}); break;
     case 5: f(std::integral_constant<int, 5>{}); break;
     case 4: f(std::integral_constant<int, 4>{}); break;
@@ -1331,18 +1342,20 @@ void with_batch_mode(bool shared, bool ukey, F&& f)
     }
 }
 
-// The loop variant of a single problem's launch (see loop_exit, loop_grid).
-int loop_of(const WalkCommon& c, bool grid)
+// The loop variant of a single problem's launch (see loop_exit, loop_grid,
+// loop_levels).
+template <class Src>
+int loop_of(const WalkCommon& c, const Src& s)
 {
     const int e = c.exit_rule == FK_EXIT_BRIDGE ? 2 : c.domain == FK_DOMAIN_BALL ? 1 : 0;
-    return e | (grid ? kLoopGrid : 0);
+    return e | (s.has_grid ? kLoopGrid : 0) | (s.has_grid && s.idx ? kLoopLevels : 0);
 }
 
 }  // namespace
 
 hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream_t stream, bool adjoint, bool dense)
 {
-    const int loop = loop_of(a.c, a.src.has_grid != 0);
+    const int loop = loop_of(a.c, a.src);
     if (adjoint)
         launch_walk<true, false, true>(a, loop, cfg, stream, dense);
     else
@@ -1353,7 +1366,7 @@ hipError_t launch_walk_f64(const WalkArgsF64& a, const LaunchCfg& cfg, hipStream
 hipError_t launch_walk_f32(const WalkArgsF32& a, bool kahan, const LaunchCfg& cfg, hipStream_t stream, bool adjoint,
                            bool dense)
 {
-    const int loop = loop_of(a.c, a.src.has_grid != 0);
+    const int loop = loop_of(a.c, a.src);
     if (adjoint) {
         if (kahan)
             launch_walk<false, true, true>(a, loop, cfg, stream, dense);

@@ -48,7 +48,8 @@ class fk_box(C.Structure):
 class fk_source(C.Structure):
     _fields_ = [("rho", C.c_void_p), ("n", C.c_int32 * 3), ("pad0", C.c_int32), ("origin", C.c_double * 3),
                 ("spacing", C.c_double * 3), ("prisms", C.c_void_p), ("n_prisms", C.c_int32), ("pad1", C.c_int32),
-                ("spheres", C.c_void_p), ("n_spheres", C.c_int32), ("pad2", C.c_int32)]
+                ("spheres", C.c_void_p), ("n_spheres", C.c_int32), ("pad2", C.c_int32),
+                ("rho_index", C.c_void_p), ("rho_levels", C.c_void_p)]
 
 
 class fk_boundary(C.Structure):
@@ -351,6 +352,21 @@ def fk_version() -> int:
 # Problem marshalling.
 # --------------------------------------------------------------------------
 
+def grid_levels(rho):
+    """An FP32 density grid as levels: (index, levels), index a uint8 array
+    of rho's shape and levels 256 float32 values with levels[index] == rho
+    element for element (unused entries NaN).  Raises ValueError for a grid
+    of more than 256 distinct values."""
+    rho = np.ascontiguousarray(np.asarray(rho, dtype=np.float32))
+    values, inverse = np.unique(rho.view(np.uint32), return_inverse=True)
+    if values.size > 256:
+        raise ValueError(f"the grid has {values.size} distinct densities; levels hold at most 256")
+    levels = np.full(256, np.nan, dtype=np.float32)
+    levels[:values.size] = values.view(np.float32)
+    index = inverse.reshape(rho.shape).astype(np.uint8)
+    return index, levels
+
+
 class Prepared:
     """Device copies and ctypes descriptors of one problem."""
 
@@ -365,9 +381,16 @@ class Prepared:
         src = fk_source()
         if prob.rho is not None and np.asarray(prob.rho).size > 0:
             rho = np.ascontiguousarray(np.asarray(prob.rho, dtype=np.float32))
-            self.rho = torch.from_numpy(rho).to(device)
             nz, ny, nx = rho.shape
-            src.rho = self.rho.data_ptr()
+            if getattr(prob, "grid_levels", False):
+                index, levels = grid_levels(rho)
+                self.rho_index = torch.from_numpy(index).to(device)
+                self.rho_levels = torch.from_numpy(levels).to(device)
+                src.rho_index = self.rho_index.data_ptr()
+                src.rho_levels = self.rho_levels.data_ptr()
+            else:
+                self.rho = torch.from_numpy(rho).to(device)
+                src.rho = self.rho.data_ptr()
             src.n = (C.c_int32 * 3)(nx, ny, nz)
             src.origin = (C.c_double * 3)(*np.asarray(prob.grid_origin, float))
             src.spacing = (C.c_double * 3)(*np.asarray(prob.grid_spacing, float))
@@ -556,6 +579,8 @@ def _gradient_function():
                 raise TypeError("rho must be a cuda float32 tensor")
             src = fk_source.from_buffer_copy(P.source)
             src.rho = rho_c.data_ptr()
+            src.rho_index = None          # the differentiable densities replace any levels
+            src.rho_levels = None
             nz, ny, nx = rho_c.shape
             src.n = (C.c_int32 * 3)(nx, ny, nz)
             nb = fk_workspace_bytes(kind, len(P.stations_host), P.params)

@@ -83,6 +83,9 @@ class Problem:
     # = bounded workspace, walks run in slices of at most that many.
     strict: int = 0
     slice_walks: int = 0
+    # the grid passed by levels (an index grid of bytes and 256 densities)
+    # instead of FP32 densities: the same densities, a quarter of the memory
+    grid_levels: bool = False
     name: str = ""
     # Prisms that the voxel grid represents exactly; kept for closed-form
     # targets only and never part of the source.

@@ -157,6 +157,16 @@ def test_bad_box_source_boundary_workspace_rejected():
     src.n = (C.c_int32 * 3)(4, 4, 4)
     src.spacing = (C.c_double * 3)(0.1, -0.1, 0.1)
     assert _call(box, src, bc, prm) == F.FK_EINVAL
+    src.spacing = (C.c_double * 3)(0.1, 0.1, 0.1)
+    src.rho_index = 2048                # the grid both as densities and by levels
+    src.rho_levels = 4096
+    assert _call(box, src, bc, prm) == F.FK_EINVAL
+    assert "not both" in L.fk_last_error().decode()
+    src.rho = None
+    src.rho_levels = None               # an index grid without its levels
+    assert _call(box, src, bc, prm) == F.FK_EINVAL
+    assert "rho_levels" in L.fk_last_error().decode()
+    src.rho_index = None
     src.rho = None
     bc.kind = 9
     assert _call(box, src, bc, prm) == F.FK_EINVAL
@@ -282,3 +292,47 @@ def test_workspace_status_rejects_null():
     assert st == F.FK_EINVAL
     assert F.fk_status_string(F.FK_ENONFINITE) != "unknown status"
     assert F.fk_status_string(F.FK_ETRUNC) != "unknown status"
+
+
+def test_batch_grids_of_one_kind():
+    """A batch's grids are all FP32 densities or all given by levels: one
+    kernel instance looks them up."""
+    arr = (F.fk_problem * 2)()
+    keep = []
+    for m in range(2):
+        _, box, src, bc, prm, k = _host_problem()
+        keep.append(k)
+        src.n = (C.c_int32 * 3)(4, 4, 4)
+        src.spacing = (C.c_double * 3)(0.5, 0.5, 0.5)
+        if m == 0:
+            src.rho = 1024
+        else:
+            src.rho_index = 2048
+            src.rho_levels = 4096
+        arr[m].kind = 0
+        arr[m].stations = 4096
+        arr[m].n_stations = 8
+        arr[m].box = box
+        arr[m].source = src
+        arr[m].bc = bc
+        arr[m].params = prm
+        arr[m].out_offset = 8 * m
+    assert F.lib().fk_batch_workspace_bytes(arr, 2) == 0
+    assert "levels" in F.lib().fk_last_error().decode()
+    arr[1].source.rho_index = None
+    arr[1].source.rho_levels = None
+    arr[1].source.rho = 1024
+    assert F.lib().fk_batch_workspace_bytes(arr, 2) > 0
+
+
+def test_grid_levels_round_trip():
+    rng = np.random.Generator(np.random.PCG64(7))
+    vals = np.array([0.0, -0.0, 1.5, 2.0e3, np.float32(1) / 3, -7.25], dtype=np.float32)
+    rho = vals[rng.integers(0, len(vals), size=(5, 6, 7))]
+    index, levels = F.grid_levels(rho)
+    assert index.dtype == np.uint8 and index.shape == rho.shape and levels.shape == (256,)
+    back = levels[index]
+    assert back.view(np.uint32).tolist() == rho.view(np.uint32).tolist()    # bit for bit, -0 kept
+    assert np.isnan(levels[len(vals):]).all()
+    with pytest.raises(ValueError):
+        F.grid_levels(np.arange(257, dtype=np.float32).reshape(1, 1, 257))
