@@ -77,13 +77,15 @@ ALGO_BYTES_PER_WALK = 36
 # for a device copy of known size.  Figures are reported only while the
 # sources still hash to the recorded value.
 COUNTERS = {
-    "sources_sha256": "a372b54c8352c18b306eef9e77c882e48a784686e5f2d18267c6f96948c004e2",
-    "cfg4_mixed": {"valu_lane_instr_per_step": 110.58825, "valu_busy": 1.103242, "fp64_flop_per_step": 2.104392, "fp32_flop_per_step": 30.680143, "fetch_kib": 991308.703125, "write_kib": 80740224.023438, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.998216},
-    "cfg4_f64": {"valu_lane_instr_per_step": 273.045588, "valu_busy": 0.939628, "fp64_flop_per_step": 143.526899, "fp32_flop_per_step": 0.06131, "fetch_kib": 802429.34375, "write_kib": 74558999.585938, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.998727},
-    "cfg2_f64": {"valu_lane_instr_per_step": 222.112118, "valu_busy": 0.980785, "fp64_flop_per_step": 108.152378, "fp32_flop_per_step": 0.073811, "fetch_kib": 169.46875, "write_kib": 875512.328125, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.874837},
-    "cfg2_mixed": {"valu_lane_instr_per_step": 84.679978, "valu_busy": 1.044448, "fp64_flop_per_step": 2.193898, "fp32_flop_per_step": 23.572416, "fetch_kib": 7850.09375, "write_kib": 1076011.984375, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.973772},
-    "cfg3_f64": {"valu_lane_instr_per_step": 268.136761, "valu_busy": 0.944927, "fp64_flop_per_step": 117.714208, "fp32_flop_per_step": 0.094086, "fetch_kib": 530431902.354167, "write_kib": 17314637.635417, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.86657},
-    "cfg3_mixed": {"valu_lane_instr_per_step": 114.446908, "valu_busy": 0.697574, "fp64_flop_per_step": 2.165511, "fp32_flop_per_step": 31.388643, "fetch_kib": 478230026.3125, "write_kib": 16339438.395833, "fetch_scale": 1.999923, "write_scale": 1.0, "l2_hit": 0.879957},
+    "sources_sha256": "b9504dcd4aa242c9ed8231d620a231cafa2035691e2bbb14710d6dc7909d8187",
+    "cfg4_mixed": {"valu_lane_instr_per_step": 110.588971, "valu_busy": 1.101225, "fp64_flop_per_step": 2.104423, "fp32_flop_per_step": 30.680605, "fetch_kib": 988733.828125, "write_kib": 80731637.328125, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.998216},
+    "cfg4_f64": {"valu_lane_instr_per_step": 273.045724, "valu_busy": 0.939742, "fp64_flop_per_step": 143.526964, "fp32_flop_per_step": 0.06131, "fetch_kib": 801141.078125, "write_kib": 74566594.617188, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.99873},
+    "cfg2_f64": {"valu_lane_instr_per_step": 222.1109, "valu_busy": 0.981597, "fp64_flop_per_step": 108.149081, "fp32_flop_per_step": 0.073727, "fetch_kib": 173.171875, "write_kib": 875704.539062, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.874856},
+    "cfg2_mixed": {"valu_lane_instr_per_step": 84.689211, "valu_busy": 1.04037, "fp64_flop_per_step": 2.194043, "fp32_flop_per_step": 23.5727, "fetch_kib": 7842.65625, "write_kib": 1078947.007812, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.973757},
+    "cfg3_f64": {"valu_lane_instr_per_step": 268.137191, "valu_busy": 0.944606, "fp64_flop_per_step": 117.714101, "fp32_flop_per_step": 0.094088, "fetch_kib": 530439384.0, "write_kib": 17314317.84375, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.866571},
+    "cfg3_mixed": {"valu_lane_instr_per_step": 114.447402, "valu_busy": 0.697686, "fp64_flop_per_step": 2.165534, "fp32_flop_per_step": 31.38883, "fetch_kib": 478226080.083333, "write_kib": 16340024.666667, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.879959},
+    "cfg3_f64_levels": {"valu_lane_instr_per_step": 266.623921, "valu_busy": 0.960239, "fp64_flop_per_step": 117.714283, "fp32_flop_per_step": 0.094086, "fetch_kib": 2821966.541667, "write_kib": 29587072.53125, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.996257},
+    "cfg3_mixed_levels": {"valu_lane_instr_per_step": 113.411746, "valu_busy": 0.816095, "fp64_flop_per_step": 2.16552, "fp32_flop_per_step": 31.388706, "fetch_kib": 162693.6875, "write_kib": 31368364.395833, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.997281},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp", "paper_1709_07469_amd/csrc/fk_stats.hpp",
