@@ -458,7 +458,7 @@ void fill_source_f32(fk::SourceF32& S, const fk_source* s)
     for (int c = 0; c < 3; ++c) {
         S.n[c] = grid ? s->n[c] : 0;
         S.nf[c] = (float)S.n[c];
-        S.origin[c] = (float)s->origin[c];
+        S.ob[c] = grid ? (float)(-s->origin[c] / s->spacing[c]) : 0.0f;
         S.inv[c] = grid ? (float)(1.0 / s->spacing[c]) : 1.0f;
     }
     S.n_prisms = s->n_prisms;

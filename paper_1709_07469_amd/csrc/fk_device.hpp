@@ -367,12 +367,18 @@ __device__ __forceinline__ double rho_f64(const SourceF64& s, double x, double y
     return bodies_f64(s, grid_f64<LEVELS>(s, x, y, z), x, y, z);
 }
 
+// FP32 voxel coordinate along one axis: floor(x / spacing - origin / spacing)
+// as one fma with both constants rounded to FP32 (inv = 1/spacing, ob =
+// -origin/spacing).  Within an ulp of floor((x - origin) / spacing); the FP32
+// walks' lookups and the mixed adjoint's voxels use this same formula.
+__device__ __forceinline__ float axis_f32(float x, float inv, float ob) { return floorf(fmaf(x, inv, ob)); }
+
 __device__ __forceinline__ int voxel_f32(const SourceF32& s, float x, float y, float z)
 {
     if (!s.has_grid) return -1;
-    const float tx = floorf((x - s.origin[0]) * s.inv[0]);
-    const float ty = floorf((y - s.origin[1]) * s.inv[1]);
-    const float tz = floorf((z - s.origin[2]) * s.inv[2]);
+    const float tx = axis_f32(x, s.inv[0], s.ob[0]);
+    const float ty = axis_f32(y, s.inv[1], s.ob[1]);
+    const float tz = axis_f32(z, s.inv[2], s.ob[2]);
     const bool in = (tx >= 0.0f) & (tx < s.nf[0]) & (ty >= 0.0f) & (ty < s.nf[1]) & (tz >= 0.0f) & (tz < s.nf[2]);
     return in ? ((int)tz * s.n[1] + (int)ty) * s.n[0] + (int)tx : -1;
 }
@@ -398,9 +404,9 @@ __device__ __forceinline__ float bodies_f32(const SourceF32& s, float r, float x
 template <bool LEVELS = false>
 __device__ __forceinline__ float grid_in_f32(const SourceF32& s, float x, float y, float z)
 {
-    const float tx = floorf((x - s.origin[0]) * s.inv[0]);
-    const float ty = floorf((y - s.origin[1]) * s.inv[1]);
-    const float tz = floorf((z - s.origin[2]) * s.inv[2]);
+    const float tx = axis_f32(x, s.inv[0], s.ob[0]);
+    const float ty = axis_f32(y, s.inv[1], s.ob[1]);
+    const float tz = axis_f32(z, s.inv[2], s.ob[2]);
     // the clamp into [0, n-1] as one median of three
     const float cx = __builtin_amdgcn_fmed3f(tx, 0.0f, s.nf[0] - 1.0f);
     const float cy = __builtin_amdgcn_fmed3f(ty, 0.0f, s.nf[1] - 1.0f);

@@ -35,8 +35,8 @@ struct SourceF32 {
     const float* levels;
     int32_t n[3];
     int32_t has_grid;
-    float origin[3];
-    float inv[3];
+    float ob[3];               // -origin / spacing
+    float inv[3];              // 1 / spacing
     float nf[3];
     int32_t n_prisms;
     int32_t n_spheres;
