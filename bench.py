@@ -77,15 +77,15 @@ ALGO_BYTES_PER_WALK = 36
 # for a device copy of known size.  Figures are reported only while the
 # sources still hash to the recorded value.
 COUNTERS = {
-    "sources_sha256": "b9504dcd4aa242c9ed8231d620a231cafa2035691e2bbb14710d6dc7909d8187",
-    "cfg4_mixed": {"valu_lane_instr_per_step": 110.588971, "valu_busy": 1.101225, "fp64_flop_per_step": 2.104423, "fp32_flop_per_step": 30.680605, "fetch_kib": 988733.828125, "write_kib": 80731637.328125, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.998216},
-    "cfg4_f64": {"valu_lane_instr_per_step": 273.045724, "valu_busy": 0.939742, "fp64_flop_per_step": 143.526964, "fp32_flop_per_step": 0.06131, "fetch_kib": 801141.078125, "write_kib": 74566594.617188, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.99873},
-    "cfg2_f64": {"valu_lane_instr_per_step": 222.1109, "valu_busy": 0.981597, "fp64_flop_per_step": 108.149081, "fp32_flop_per_step": 0.073727, "fetch_kib": 173.171875, "write_kib": 875704.539062, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.874856},
-    "cfg2_mixed": {"valu_lane_instr_per_step": 84.689211, "valu_busy": 1.04037, "fp64_flop_per_step": 2.194043, "fp32_flop_per_step": 23.5727, "fetch_kib": 7842.65625, "write_kib": 1078947.007812, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.973757},
-    "cfg3_f64": {"valu_lane_instr_per_step": 268.137191, "valu_busy": 0.944606, "fp64_flop_per_step": 117.714101, "fp32_flop_per_step": 0.094088, "fetch_kib": 530439384.0, "write_kib": 17314317.84375, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.866571},
-    "cfg3_mixed": {"valu_lane_instr_per_step": 114.447402, "valu_busy": 0.697686, "fp64_flop_per_step": 2.165534, "fp32_flop_per_step": 31.38883, "fetch_kib": 478226080.083333, "write_kib": 16340024.666667, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.879959},
-    "cfg3_f64_levels": {"valu_lane_instr_per_step": 266.623921, "valu_busy": 0.960239, "fp64_flop_per_step": 117.714283, "fp32_flop_per_step": 0.094086, "fetch_kib": 2821966.541667, "write_kib": 29587072.53125, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.996257},
-    "cfg3_mixed_levels": {"valu_lane_instr_per_step": 113.411746, "valu_busy": 0.816095, "fp64_flop_per_step": 2.16552, "fp32_flop_per_step": 31.388706, "fetch_kib": 162693.6875, "write_kib": 31368364.395833, "fetch_scale": 1.999925, "write_scale": 1.0, "l2_hit": 0.997281},
+    "sources_sha256": "f62502d3529eca42fc0bf3261973b375b44d728d309a559619520bc0ece6f822",
+    "cfg4_mixed": {"valu_lane_instr_per_step": 108.16996, "valu_busy": 1.091188, "fp64_flop_per_step": 2.104391, "fp32_flop_per_step": 30.68011, "fetch_kib": 983853.125, "write_kib": 80741379.320312, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.99822},
+    "cfg4_f64": {"valu_lane_instr_per_step": 273.045701, "valu_busy": 0.9397, "fp64_flop_per_step": 143.527018, "fp32_flop_per_step": 0.06131, "fetch_kib": 803837.46875, "write_kib": 74560463.710938, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.998729},
+    "cfg2_f64": {"valu_lane_instr_per_step": 222.112173, "valu_busy": 0.977391, "fp64_flop_per_step": 108.152058, "fp32_flop_per_step": 0.073697, "fetch_kib": 173.09375, "write_kib": 875728.65625, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.874856},
+    "cfg2_mixed": {"valu_lane_instr_per_step": 84.679799, "valu_busy": 1.047813, "fp64_flop_per_step": 2.194113, "fp32_flop_per_step": 23.573059, "fetch_kib": 7843.53125, "write_kib": 1080410.085938, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.973796},
+    "cfg3_f64": {"valu_lane_instr_per_step": 268.136251, "valu_busy": 0.94474, "fp64_flop_per_step": 117.714184, "fp32_flop_per_step": 0.094087, "fetch_kib": 530427727.458333, "write_kib": 17314434.90625, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.86657},
+    "cfg3_mixed": {"valu_lane_instr_per_step": 112.046332, "valu_busy": 0.683603, "fp64_flop_per_step": 2.16552, "fp32_flop_per_step": 31.388704, "fetch_kib": 478212842.645833, "write_kib": 16338305.65625, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.87996},
+    "cfg3_f64_levels": {"valu_lane_instr_per_step": 266.624667, "valu_busy": 0.960222, "fp64_flop_per_step": 117.714334, "fp32_flop_per_step": 0.094088, "fetch_kib": 2825505.125, "write_kib": 29589589.822917, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.996256},
+    "cfg3_mixed_levels": {"valu_lane_instr_per_step": 111.011342, "valu_busy": 0.803178, "fp64_flop_per_step": 2.165514, "fp32_flop_per_step": 31.388701, "fetch_kib": 162974.0, "write_kib": 31368859.854167, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.99728},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp", "paper_1709_07469_amd/csrc/fk_stats.hpp",

@@ -57,6 +57,9 @@ def test_static_with_a_slice_bound_and_a_grid():
     ref, _, _ = F.solve(pr, 0)
     got = _static(pr.replace(slice_walks=3 * 8192 + 5), 0)
     assert got.tobytes() == ref.tobytes()
+    # the same grid given by levels (a byte per voxel and its densities)
+    got = _static(pr.replace(slice_walks=3 * 8192 + 5, grid_levels=True), 0)
+    assert got.tobytes() == ref.tobytes()
 
 
 def test_static_refuses_what_does_not_fit():
