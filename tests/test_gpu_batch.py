@@ -31,10 +31,15 @@ def _small_mix(precision):
 
 
 @pytest.mark.parametrize("precision", [W.PREC_F64, W.PREC_MIXED_F64ACC, W.PREC_MIXED_KAHAN])
-def test_batch_equals_standalone_bitwise(precision):
+@pytest.mark.parametrize("seeds", ["one", "per_problem"])
+def test_batch_equals_standalone_bitwise(precision, seeds):
+    """One seed for the whole batch (mixed batches then hold the generator key
+    in scalar registers) and a seed per problem (each lane its own key)."""
     from paper_1709_07469_amd import fkgrav as F
     probs, kinds = _small_mix(precision)
-    say("batch of", len(probs), "precision", precision)
+    if seeds == "per_problem":
+        probs = [p.replace(seed=(0x9E3779B97F4A7C15 * (m + 1)) % (1 << 64)) for m, p in enumerate(probs)]
+    say("batch of", len(probs), "precision", precision, "seeds", seeds)
     res, ws, PB, _ = F.solve_batch(probs, kinds)
     for m, (p, k) in enumerate(zip(probs, kinds)):
         alone, ws1, P1 = F.solve(p, k)
