@@ -168,9 +168,13 @@ def closed_form_error(mean, se, exact):
             "median_rel_se": float(np.median(se / np.abs(exact)))}
 
 
+_T0 = time.time()
+
+
 def log(*a):
-    """A progress line on stderr (the JSON line alone goes to stdout)."""
-    print("bench:", *a, file=sys.stderr, flush=True)
+    """A progress line on stderr (the JSON line alone goes to stdout), with
+    the seconds since the start."""
+    print(f"bench: [{time.time() - _T0:.0f} s]", *a, file=sys.stderr, flush=True)
 
 
 def load_targets():
