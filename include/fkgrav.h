@@ -124,7 +124,9 @@ typedef struct {
 /* Density rho(x) (paper eq. 4), the sum of
  *   - a voxel grid: rho (DEVICE, float, [n[2]][n[1]][n[0]], x fastest; NULL
  *     for none); voxel (i,j,k) is [origin + (i,j,k)*spacing, origin +
- *     (i+1,j+1,k+1)*spacing), zero outside the grid.  Or the same grid given
+ *     (i+1,j+1,k+1)*spacing), zero outside the grid; each n[c] at most
+ *     2^24 - 1 and the grid at most 2^31 - 1 voxels (FK_EUNSUPPORTED
+ *     beyond).  Or the same grid given
  *     by levels: rho_index (DEVICE, uint8, the same layout) selects the
  *     voxel's density rho_levels[rho_index] (DEVICE, 256 floats: any byte
  *     indexes inside it; entries no voxel selects are never read), with rho

@@ -287,7 +287,7 @@ fk_status check_source(const fk_source* s)
         int64_t nv = 1;
         for (int c = 0; c < 3; ++c) {
             if (s->n[c] < 1) return fail(FK_EINVAL, "grid size n[%d] must be >= 1", c);
-            if (s->n[c] > (1 << 24)) return fail(FK_EUNSUPPORTED, "grid size n[%d] must be <= 2^24", c);
+            if (s->n[c] >= (1 << 24)) return fail(FK_EUNSUPPORTED, "grid size n[%d] must be < 2^24", c);
             if (!(is_finite(s->spacing[c]) && s->spacing[c] > 0.0)) return fail(FK_EINVAL, "grid spacing must be > 0");
             if (!is_finite(s->origin[c])) return fail(FK_EINVAL, "grid origin must be finite");
             nv *= s->n[c];
@@ -439,6 +439,7 @@ void fill_source_f64(fk::SourceF64& S, const fk_source* s)
         S.inv[c] = 1.0 / S.spacing[c];
         S.exact[c] = power_of_two(S.spacing[c]);
     }
+    S.nxy = grid ? (uint32_t)((int64_t)S.n[0] * S.n[1]) : 0u;
     S.n_prisms = s->n_prisms;
     S.n_spheres = s->n_spheres;
     for (int j = 0; j < s->n_prisms; ++j)
@@ -457,10 +458,10 @@ void fill_source_f32(fk::SourceF32& S, const fk_source* s)
     S.has_grid = grid;
     for (int c = 0; c < 3; ++c) {
         S.n[c] = grid ? s->n[c] : 0;
-        S.nf[c] = (float)S.n[c];
         S.ob[c] = grid ? (float)(-s->origin[c] / s->spacing[c]) : 0.0f;
         S.inv[c] = grid ? (float)(1.0 / s->spacing[c]) : 1.0f;
     }
+    S.nxy = grid ? (uint32_t)((int64_t)S.n[0] * S.n[1]) : 0u;
     S.n_prisms = s->n_prisms;
     S.n_spheres = s->n_spheres;
     for (int j = 0; j < s->n_prisms; ++j)

@@ -326,31 +326,92 @@ __device__ __forceinline__ double bodies_f64(const SourceF64& s, double r, doubl
     return r;
 }
 
+// A floored coordinate as an int (v_cvt_i32_f64): exact for integers in the
+// int range, saturating to INT_MIN or INT_MAX beyond it, which in_axis reads
+// as outside.
+__device__ __forceinline__ int floor_to_i32(double t)
+{
+    int i;
+    asm("v_cvt_i32_f64 %0, %1" : "=v"(i) : "v"(t));
+    return i;
+}
+
+// 0 <= i < n as one unsigned compare.
+__device__ __forceinline__ bool in_axis(int i, int n) { return (uint32_t)i < (uint32_t)n; }
+
 // The voxel grid's density at (x, y, z): zero outside the grid or without one
-// (the same voxel as voxel_f64).  Branch-free, so that several lookups can be
-// in flight at once: each floored coordinate t is clamped into [0, n-1] --
-// t lies in the grid exactly when the clamp leaves it unchanged (t is an
-// integer; a NaN never compares equal) -- and the load always reads a voxel
-// of the grid, its value dropped outside.  A voxel value of -0 may come back
-// as -0 where the other paths give +0: no sum of densities can tell them apart
-// (the walk's sums start at +0).  The host limits a grid to 2^31 - 1
-// voxels, so the flat index fits 32 bits.  LEVELS: the grid is given by
-// levels, the voxel's density levels[idx[v]] (two dependent loads; the index
-// grid is a quarter of the FP32 grid's size).
+// (the same voxel as voxel_f64).  Branch-free, and in two halves so that a
+// run of lookups has all its loads in flight before the first value is used:
+// fetch floors the coordinates to ints and loads the voxel's value, each
+// index clamped into the grid so that the load always reads one of its
+// voxels; keep drops the value unless all three indices lie in the grid (one
+// unsigned compare each).  A voxel value of -0 may come back as -0 where the
+// other paths give +0: no sum of densities can tell them apart (the walk's
+// sums start at +0).  Positions are finite (walks start at finite stations
+// and take bounded steps inside the box).  LEVELS: the grid is given by
+// levels, the voxel's density levels[idx[v]]; fetch loads the level and keep
+// its density (the index grid is a quarter of the FP32 grid's size).
 // grid_in_* need a grid (has_grid); grid_* check for one.
+struct GridProbe {
+    float r;      // the voxel's density (FP32 grid)
+    uint32_t b;   // or its level (grid by levels)
+    int i[3];     // the floored indices, possibly outside the grid
+};
+
+// The flat index of indices i clamped into the grid; an index outside it
+// becomes some voxel of the grid.  The row offset is a 24-bit multiply-add
+// (the host limits each axis to fewer than 2^24 voxels) and the layer offset
+// a 64-bit one.
+template <class Src>
+__device__ __forceinline__ uint64_t probe_index(const Src& s, const int* i)
+{
+    const uint32_t cx = min((uint32_t)i[0], (uint32_t)s.n[0] - 1u);
+    const uint32_t cy = min((uint32_t)i[1], (uint32_t)s.n[1] - 1u);
+    const uint32_t cz = min((uint32_t)i[2], (uint32_t)s.n[2] - 1u);
+    uint64_t v = (uint64_t)cz * s.nxy + (__umul24(cy, (uint32_t)s.n[0]) + cx);
+    asm("" : "+v"(v));   // one index, one address: the sum is not split
+    return v;
+}
+
+template <bool LEVELS, class Src>
+__device__ __forceinline__ void probe_load(const Src& s, GridProbe& p)
+{
+    const uint64_t v = probe_index(s, p.i);
+    if (LEVELS)
+        p.b = s.idx[v];
+    else
+        p.r = s.rho[v];
+}
+
+template <bool LEVELS, class Src>
+__device__ __forceinline__ float probe_keep(const Src& s, const GridProbe& p)
+{
+    const bool in = in_axis(p.i[0], s.n[0]) & in_axis(p.i[1], s.n[1]) & in_axis(p.i[2], s.n[2]);
+    const float r = LEVELS ? s.levels[p.b] : p.r;
+    return in ? r : 0.0f;
+}
+
+template <bool LEVELS = false>
+__device__ __forceinline__ GridProbe grid_fetch_f64(const SourceF64& s, double x, double y, double z)
+{
+    GridProbe p;
+    p.i[0] = floor_to_i32(grid_axis_f64(x, s.origin[0], s.spacing[0], s.inv[0], s.exact[0]));
+    p.i[1] = floor_to_i32(grid_axis_f64(y, s.origin[1], s.spacing[1], s.inv[1], s.exact[1]));
+    p.i[2] = floor_to_i32(grid_axis_f64(z, s.origin[2], s.spacing[2], s.inv[2], s.exact[2]));
+    probe_load<LEVELS>(s, p);
+    return p;
+}
+
+template <bool LEVELS = false>
+__device__ __forceinline__ double grid_keep_f64(const SourceF64& s, const GridProbe& p)
+{
+    return (double)probe_keep<LEVELS>(s, p);
+}
+
 template <bool LEVELS = false>
 __device__ __forceinline__ double grid_in_f64(const SourceF64& s, double x, double y, double z)
 {
-    const double tx = grid_axis_f64(x, s.origin[0], s.spacing[0], s.inv[0], s.exact[0]);
-    const double ty = grid_axis_f64(y, s.origin[1], s.spacing[1], s.inv[1], s.exact[1]);
-    const double tz = grid_axis_f64(z, s.origin[2], s.spacing[2], s.inv[2], s.exact[2]);
-    const double cx = fmin(fmax(tx, 0.0), (double)(s.n[0] - 1));
-    const double cy = fmin(fmax(ty, 0.0), (double)(s.n[1] - 1));
-    const double cz = fmin(fmax(tz, 0.0), (double)(s.n[2] - 1));
-    const bool in = (cx == tx) & (cy == ty) & (cz == tz);
-    const uint32_t v = ((uint32_t)cz * (uint32_t)s.n[1] + (uint32_t)cy) * (uint32_t)s.n[0] + (uint32_t)cx;
-    const float r = LEVELS ? s.levels[s.idx[v]] : s.rho[v];
-    return in ? (double)r : 0.0;
+    return grid_keep_f64<LEVELS>(s, grid_fetch_f64<LEVELS>(s, x, y, z));
 }
 
 // LEVELS: the kernel's grids are given by levels (a compile-time property
@@ -367,20 +428,33 @@ __device__ __forceinline__ double rho_f64(const SourceF64& s, double x, double y
     return bodies_f64(s, grid_f64<LEVELS>(s, x, y, z), x, y, z);
 }
 
-// FP32 voxel coordinate along one axis: floor(x / spacing - origin / spacing)
-// as one fma with both constants rounded to FP32 (inv = 1/spacing, ob =
+// floor(x) as an int in one instruction (v_cvt_flr_i32_f32 rounds toward
+// -infinity while it converts).  Equal to (int)floorf(x) for finite x in the
+// int range; beyond it the result saturates to INT_MIN or INT_MAX, which the
+// unsigned compare of in_axis reads as outside.
+__device__ __forceinline__ int floor_i32(float x)
+{
+    int i;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(x));
+    return i;
+}
+
+// FP32 voxel index along one axis: floor(x / spacing - origin / spacing)
+// from one fma with both constants rounded to FP32 (inv = 1/spacing, ob =
 // -origin/spacing).  Within an ulp of floor((x - origin) / spacing); the FP32
 // walks' lookups and the mixed adjoint's voxels use this same formula.
-__device__ __forceinline__ float axis_f32(float x, float inv, float ob) { return floorf(fmaf(x, inv, ob)); }
+// Positions are finite: walks start at finite stations and take bounded
+// steps inside the box.
+__device__ __forceinline__ int axis_f32(float x, float inv, float ob) { return floor_i32(fmaf(x, inv, ob)); }
 
 __device__ __forceinline__ int voxel_f32(const SourceF32& s, float x, float y, float z)
 {
     if (!s.has_grid) return -1;
-    const float tx = axis_f32(x, s.inv[0], s.ob[0]);
-    const float ty = axis_f32(y, s.inv[1], s.ob[1]);
-    const float tz = axis_f32(z, s.inv[2], s.ob[2]);
-    const bool in = (tx >= 0.0f) & (tx < s.nf[0]) & (ty >= 0.0f) & (ty < s.nf[1]) & (tz >= 0.0f) & (tz < s.nf[2]);
-    return in ? ((int)tz * s.n[1] + (int)ty) * s.n[0] + (int)tx : -1;
+    const int ix = axis_f32(x, s.inv[0], s.ob[0]);
+    const int iy = axis_f32(y, s.inv[1], s.ob[1]);
+    const int iz = axis_f32(z, s.inv[2], s.ob[2]);
+    const bool in = in_axis(ix, s.n[0]) & in_axis(iy, s.n[1]) & in_axis(iz, s.n[2]);
+    return in ? (iz * s.n[1] + iy) * s.n[0] + ix : -1;
 }
 
 __device__ __forceinline__ float bodies_f32(const SourceF32& s, float r, float x, float y, float z, int j0 = 0)
@@ -399,22 +473,29 @@ __device__ __forceinline__ float bodies_f32(const SourceF32& s, float r, float x
     return r;
 }
 
-// FP32 stepping's grid lookup, branch-free like grid_f64 (the same voxel as
-// voxel_f32).
+// FP32 stepping's grid lookup, branch-free like grid_in_f64 (the same voxel
+// as voxel_f32).
+template <bool LEVELS = false>
+__device__ __forceinline__ GridProbe grid_fetch_f32(const SourceF32& s, float x, float y, float z)
+{
+    GridProbe p;
+    p.i[0] = axis_f32(x, s.inv[0], s.ob[0]);
+    p.i[1] = axis_f32(y, s.inv[1], s.ob[1]);
+    p.i[2] = axis_f32(z, s.inv[2], s.ob[2]);
+    probe_load<LEVELS>(s, p);
+    return p;
+}
+
+template <bool LEVELS = false>
+__device__ __forceinline__ float grid_keep_f32(const SourceF32& s, const GridProbe& p)
+{
+    return probe_keep<LEVELS>(s, p);
+}
+
 template <bool LEVELS = false>
 __device__ __forceinline__ float grid_in_f32(const SourceF32& s, float x, float y, float z)
 {
-    const float tx = axis_f32(x, s.inv[0], s.ob[0]);
-    const float ty = axis_f32(y, s.inv[1], s.ob[1]);
-    const float tz = axis_f32(z, s.inv[2], s.ob[2]);
-    // the clamp into [0, n-1] as one median of three
-    const float cx = __builtin_amdgcn_fmed3f(tx, 0.0f, s.nf[0] - 1.0f);
-    const float cy = __builtin_amdgcn_fmed3f(ty, 0.0f, s.nf[1] - 1.0f);
-    const float cz = __builtin_amdgcn_fmed3f(tz, 0.0f, s.nf[2] - 1.0f);
-    const bool in = (cx == tx) & (cy == ty) & (cz == tz);
-    const uint32_t v = ((uint32_t)cz * (uint32_t)s.n[1] + (uint32_t)cy) * (uint32_t)s.n[0] + (uint32_t)cx;
-    const float r = LEVELS ? s.levels[s.idx[v]] : s.rho[v];
-    return in ? r : 0.0f;
+    return grid_keep_f32<LEVELS>(s, grid_fetch_f32<LEVELS>(s, x, y, z));
 }
 
 template <bool LEVELS = false>

@@ -24,7 +24,7 @@ struct SourceF64 {
     int32_t exact[3];          // spacing is a power of two: (x - o) * inv == (x - o) / spacing
     int32_t n_prisms;
     int32_t n_spheres;
-    int32_t pad0;
+    uint32_t nxy;              // n[0] n[1], the voxels of one layer
     double prisms[FK_MAX_PRISMS][7];
     double spheres[FK_MAX_SPHERES][5];
 };
@@ -37,7 +37,7 @@ struct SourceF32 {
     int32_t has_grid;
     float ob[3];               // -origin / spacing
     float inv[3];              // 1 / spacing
-    float nf[3];
+    uint32_t nxy;              // n[0] n[1], the voxels of one layer
     int32_t n_prisms;
     int32_t n_spheres;
     int32_t pad0;

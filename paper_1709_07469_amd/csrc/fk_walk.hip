@@ -346,6 +346,10 @@ struct Prec<true> {
     __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f64<LEVELS>(s, x, y, z); }
     template <bool LEVELS>
     __device__ static T grid_in(const Src& s, T x, T y, T z) { return grid_in_f64<LEVELS>(s, x, y, z); }
+    template <bool LEVELS>
+    __device__ static GridProbe grid_fetch(const Src& s, T x, T y, T z) { return grid_fetch_f64<LEVELS>(s, x, y, z); }
+    template <bool LEVELS>
+    __device__ static T grid_keep(const Src& s, const GridProbe& p) { return grid_keep_f64<LEVELS>(s, p); }
     __device__ static T bodies(const Src& s, T g, T x, T y, T z, int j0 = 0) { return bodies_f64(s, g, x, y, z, j0); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f64(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo[c]; }
@@ -380,6 +384,10 @@ struct Prec<false> {
     __device__ static T rho(const Src& s, T x, T y, T z) { return rho_f32<LEVELS>(s, x, y, z); }
     template <bool LEVELS>
     __device__ static T grid_in(const Src& s, T x, T y, T z) { return grid_in_f32<LEVELS>(s, x, y, z); }
+    template <bool LEVELS>
+    __device__ static GridProbe grid_fetch(const Src& s, T x, T y, T z) { return grid_fetch_f32<LEVELS>(s, x, y, z); }
+    template <bool LEVELS>
+    __device__ static T grid_keep(const Src& s, const GridProbe& p) { return grid_keep_f32<LEVELS>(s, p); }
     __device__ static T bodies(const Src& s, T g, T x, T y, T z, int j0 = 0) { return bodies_f32(s, g, x, y, z, j0); }
     __device__ static int64_t voxel(const Src& s, T x, T y, T z) { return voxel_f32(s, x, y, z); }
     __device__ static T lo(const WalkCommon& C, int c) { return C.lo_f[c]; }
@@ -579,9 +587,12 @@ struct Walker {
         // but a batch may mix sources with and without one: the lane's own
         // source is checked, once for all the macro-step's loads.
         if (!ADJ && loop_grid(LOOP) && src.has_grid) {
+            GridProbe pr[MACRO];
 #pragma unroll
             for (int s = 0; s < MACRO; ++s)
-                g[s] = Prec<F64>::template grid_in<loop_levels(LOOP)>(src, z[3 * s], z[3 * s + 1], z[3 * s + 2]);
+                pr[s] = Prec<F64>::template grid_fetch<loop_levels(LOOP)>(src, z[3 * s], z[3 * s + 1], z[3 * s + 2]);
+#pragma unroll
+            for (int s = 0; s < MACRO; ++s) g[s] = Prec<F64>::template grid_keep<loop_levels(LOOP)>(src, pr[s]);
         }
     }
 

@@ -128,7 +128,6 @@ def test_bad_params_rejected(field, value, status):
 
 
 @host_only
-@host_only
 def test_ball_and_bridge_arguments_rejected():
     pr, box, src, bc, prm, keep = _host_problem()
     prm.domain = 1                      # a ball needs a cubic box
@@ -158,6 +157,13 @@ def test_bad_box_source_boundary_workspace_rejected():
     src.spacing = (C.c_double * 3)(0.1, -0.1, 0.1)
     assert _call(box, src, bc, prm) == F.FK_EINVAL
     src.spacing = (C.c_double * 3)(0.1, 0.1, 0.1)
+    src.n = (C.c_int32 * 3)(1, 1 << 24, 1)  # an axis of 2^24 voxels (the row offset is a 24-bit product)
+    assert _call(box, src, bc, prm) == F.FK_EUNSUPPORTED
+    assert "2^24" in L.fk_last_error().decode()
+    src.n = (C.c_int32 * 3)((1 << 24) - 1, 1 << 7, 2)   # 2^32 - 2^8 voxels
+    assert _call(box, src, bc, prm) == F.FK_EUNSUPPORTED
+    assert "2^31-1 voxels" in L.fk_last_error().decode()
+    src.n = (C.c_int32 * 3)(4, 4, 4)
     src.rho_index = 2048                # the grid both as densities and by levels
     src.rho_levels = 4096
     assert _call(box, src, bc, prm) == F.FK_EINVAL

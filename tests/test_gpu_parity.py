@@ -80,6 +80,47 @@ def test_f64_voxel_grid_parity_general_spacing():
     _check_f64_potential(pr.replace(paths_per_station=300, stations=pr.stations[:12]))
 
 
+def _subgrid(precision, n_walks):
+    """A 12 x 9 x 7 grid of uneven spacing over the middle of the box
+    [-1, 1]^3, with stations inside and outside it: walks cross each of its
+    six faces, so the lookup meets indices below 0 and at or past n on every
+    axis, and points on no voxel's corner."""
+    rng = np.random.default_rng(21)
+    n = np.array([12, 9, 7])
+    o = np.array([-0.61, -0.47, -0.53])
+    d = np.array([0.1, 0.11, 0.13])
+    rho = rng.choice(np.array([0.0, 0.5, 0.9, 1.3, 1.7, 2.0], dtype=np.float32), size=n[::-1])   # 6 levels
+    st = np.array([[0.0, 0.0, 0.0], [-0.55, 0.4, 0.3], [0.5, -0.45, -0.5], [0.8, 0.75, 0.0], [-0.85, -0.2, 0.7]])
+    return W.Problem(box_lo=np.full(3, -1.0), box_hi=np.full(3, 1.0), stations=st, dt=1e-3,
+                     paths_per_station=n_walks, seed=5, G=0.9, rho=rho, grid_origin=o, grid_spacing=d,
+                     precision=precision, name="subgrid")
+
+
+def test_f64_voxel_grid_inside_the_box_parity():
+    _check_f64_potential(_subgrid(W.PREC_F64, 400))
+
+
+@pytest.mark.parametrize("precision", [W.PREC_MIXED_F64ACC, W.PREC_MIXED_KAHAN])
+def test_mixed_voxel_grid_inside_the_box_against_oracle_fp32_stream(precision):
+    # the FP32 lookup (one fma per axis) may pick the neighbouring voxel
+    # within an ulp of a face; everything else matches the oracle's walks
+    pr = _subgrid(precision, 3000)
+    say("case mixed subgrid", precision)
+    stats, gv, gs = gpu_solve(pr, 0)
+    ost, ou, osteps = oracle.solve(pr, 0, stream=oracle.STREAM_F32)
+    frac = float(np.mean(gs != osteps))
+    say("  step mismatch fraction", frac)
+    assert frac < 0.02
+    same = gs == osteps
+    rel = np.abs(gv - ou)[same] / np.maximum(np.abs(ou)[same], 1e-300)
+    say("  median / 99.9% rel diff of matching walks", np.median(rel), np.quantile(rel, 0.999))
+    assert np.quantile(rel, 0.999) < 1e-4
+    for s in range(pr.n_stations):
+        assert abs(stats["mean"][s] - ost[s]["mean"]) < 0.5 * ost[s]["se"]
+    lv, _, _ = gpu_solve(pr.replace(grid_levels=True), 0)
+    assert np.asarray(lv).tobytes() == np.asarray(stats).tobytes()
+
+
 _HARM = np.array([0.4, 1.0, -0.5, 0.25, 0.2, 0.0, 0.3, -0.3, -0.1, 0.1])
 _BOX = dict(box_lo=np.array([-1.0, -1.0, -1.0]), box_hi=np.array([1.0, 1.0, 1.0]))
 _ST4 = np.array([[0.0, 0.0, 0.0], [0.5, -0.3, 0.2], [-0.7, 0.6, -0.4], [0.1, 0.85, 0.7]])
