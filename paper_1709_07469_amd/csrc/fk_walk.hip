@@ -982,7 +982,11 @@ __device__ __forceinline__ void walk_body(const Args& A)
                     W.sc.sign = ti.w ? -1 : 1;
                     W.sc.add(Prec<F64>::voxel(source(), W.x0, W.x1, W.x2), 1);
                 } else {
-                    W.rp = Prec<F64>::template rho<loop_levels(LOOP)>(source(), W.x0, W.x1, W.x2);
+                    // a launch without the grid loop has no grid in any source
+                    if constexpr (loop_grid(LOOP))
+                        W.rp = Prec<F64>::template rho<loop_levels(LOOP)>(source(), W.x0, W.x1, W.x2);
+                    else
+                        W.rp = Prec<F64>::bodies(source(), T(0), W.x0, W.x1, W.x2);
                 }
                 W.deep = false;
                 if (loop_exit(LOOP) == 2 && P.bridge) {
