@@ -685,21 +685,40 @@ __device__ __forceinline__ double atan2_q(double n, double d, const AtanTable& A
 
 // F(X, Y, Z) below has the cyclic form sum over (u, v, w) of
 // u v ln(w + r) - (u^2 / 2) atan(v w / (u r)), (u, v, w) = (X, Y, Z), (Y, Z, X),
-// (Z, X, Y).  Along a prism edge only w changes, so the difference of one such
-// pair of terms between the edge's upper corner (w_u, r_u) and lower corner
-// (w_l, r_l) takes one logarithm and one arctangent:
-//   u v ln((w_u + r_u) / (w_l + r_l))
-//   - (u^2 / 2) atan2(u v (w_u r_l - w_l r_u), u^2 r_u r_l + v^2 w_u w_l)
-// (atan p - atan q = atan2(p - q, 1 + p q), here multiplied through by
-// u^2 r_u r_l > 0).  A term whose prefactor u v or u is zero vanishes.
-__device__ __forceinline__ double edge_terms(double u, double v, double wl, double wu, double rl, double ru, double u2,
-                                             double v2, const BmTables& T, const AtanTable& A)
+// (Z, X, Y).  Along a prism edge only w changes, so the difference of the
+// logarithmic term between the edge's upper corner (w_u, r_u) and lower
+// corner (w_l, r_l) takes one logarithm, u v ln((w_u + r_u) / (w_l + r_l));
+// it vanishes when u v = 0.  s = u^2 + v^2.
+__device__ __forceinline__ double edge_log(double u, double v, double wl, double wu, double rl, double ru, double s,
+                                           const BmTables& T)
 {
     const double uv = u * v;
-    const double s = u2 + v2;
     const double l = uv * ln_ratio(shift_quot(wu, ru, s), shift_quot(wl, rl, s), T);
-    const double t = 0.5 * u2 * atan2_q(uv * (wu * rl - wl * ru), u2 * (ru * rl) + v2 * (wu * wl), A);
-    return ((uv != 0.0) ? l : 0.0) - ((u != 0.0) ? t : 0.0);
+    return (uv != 0.0) ? l : 0.0;
+}
+
+// The arctangent terms of one face of the prism, the plane u = U with corners
+// (v_j, w_k): half of sum_jk (-1)^(j+k) atan(v_j w_k / (|U| r_jk)), which is
+// the solid angle the face subtends from p, halved, for U > 0.  atan(q / p)
+// with p = |U| r > 0 and q = v w is twice the argument of
+// h = (|c| + p) + i q, |c| = sqrt(p^2 + q^2) = d_v d_w (the distances
+// sqrt(U^2 + v^2) and sqrt(U^2 + w^2) in the face's two coordinate planes),
+// and that argument lies in (-pi/4, pi/4).  The four arguments with their
+// signs add up to the argument of h00 conj(h01) conj(h10) h11, in (-pi, pi):
+// one atan2 per face.  au = |U|; vw[j][k] = v_j w_k.
+__device__ __forceinline__ double face_half_angle(double au, const double (&r)[2][2], const double (&dv)[2],
+                                                  const double (&dw)[2], const double (&vw)[2][2], const AtanTable& A)
+{
+    double re[2][2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) re[j][k] = fma(au, r[j][k], dv[j] * dw[k]);
+    const double ar = fma(re[0][0], re[0][1], vw[0][0] * vw[0][1]);      // h00 conj(h01)
+    const double ai = fma(vw[0][0], re[0][1], -(re[0][0] * vw[0][1]));
+    const double br = fma(re[1][1], re[1][0], vw[1][1] * vw[1][0]);      // h11 conj(h10)
+    const double bi = fma(vw[1][1], re[1][0], -(re[1][1] * vw[1][0]));
+    return atan2_q(fma(ar, bi, ai * br), fma(ar, br, -(ai * bi)), A);
 }
 
 // Newtonian integral of the unit-density prism [lo, hi] seen from p: the
@@ -708,15 +727,17 @@ __device__ __forceinline__ double edge_terms(double u, double v, double wl, doub
 //   - X^2/2 atan(YZ/(Xr)) - Y^2/2 atan(ZX/(Yr)) - Z^2/2 atan(XY/(Zr))
 // with corner (X, Y, Z) = corner - p and sign + at the corners with an odd
 // number of upper coordinates (Nagy, Papp & Benedek 2000); a term whose
-// prefactor is zero vanishes.  The corners are taken in pairs along each of
-// the 12 edges, each edge carrying the two terms whose prefactors stay fixed
-// along it (edge_terms): 8 square roots (sqrt_nonneg, from the hardware
-// reciprocal square root: a corner distance is zero or far above the
-// subnormal range), 12 logarithms and 12 arctangents
-// instead of 24 of each, and no cancellation between the two corners' large
-// logarithms and angles.  Every term is evaluated and the vanishing ones
-// selected away (their logarithm or quotient may be infinite), so the lanes
-// of a wavefront -- whose exit points differ -- take no branches.
+// prefactor is zero vanishes.  The logarithms are taken in pairs along each
+// of the 12 edges (edge_log) and the arctangents by face: the face U = U_a
+// contributes (-1)^a U_a |U_a| times its half angle (face_half_angle).  That
+// is 8 corner distances and 12 in-plane ones (sqrt_nonneg, from the hardware
+// reciprocal square root: a distance is zero or far above the subnormal
+// range), 12 logarithms and 6 arctangents instead of 24 of each, with no
+// cancellation between the two corners' large logarithms.  Every term is
+// evaluated and the vanishing ones selected away (their logarithm or
+// quotient may be infinite), so the lanes of a wavefront -- whose exit
+// points differ -- take no branches.  The face products are of degree 8 in
+// the coordinates: exact for |coordinates| up to about 1e37.
 __device__ inline double prism_newton(const double* q, double px, double py, double pz, const DataTables& tb)
 {
     const BmTables& T = *tb.bm;
@@ -728,23 +749,48 @@ __device__ inline double prism_newton(const double* q, double px, double py, dou
     const double Y2[2] = {Y[0] * Y[0], Y[1] * Y[1]};
     const double Z2[2] = {Z[0] * Z[0], Z[1] * Z[1]};
     double r[2][2][2];   // r[i][j][k] at corner (X[i], Y[j], Z[k])
+    double dxy[2][2], dyz[2][2], dzx[2][2];   // dxy[i][j] = |(X[i], Y[j])|, dyz[j][k], dzx[k][i]
+    double xy[2][2], yz[2][2], zx[2][2];      // xy[i][j] = X[i] Y[j], ...
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) {
+            dxy[i][j] = sqrt_nonneg(X2[i] + Y2[j]);
+            dyz[i][j] = sqrt_nonneg(Y2[i] + Z2[j]);
+            dzx[i][j] = sqrt_nonneg(Z2[i] + X2[j]);
+            xy[i][j] = X[i] * Y[j];
+            yz[i][j] = Y[i] * Z[j];
+            zx[i][j] = Z[i] * X[j];
 #pragma unroll
             for (int k = 0; k < 2; ++k) r[i][j][k] = sqrt_nonneg(X2[i] + Y2[j] + Z2[k]);
+        }
     double v = 0.0;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             // an edge's upper corner has a + b + 1 upper coordinates: sign + when that is odd
-            double e = edge_terms(X[a], Y[b], Z[0], Z[1], r[a][b][0], r[a][b][1], X2[a], Y2[b], T, A);   // along z
-            e += edge_terms(Y[a], Z[b], X[0], X[1], r[0][a][b], r[1][a][b], Y2[a], Z2[b], T, A);          // along x
-            e += edge_terms(Z[a], X[b], Y[0], Y[1], r[b][0][a], r[b][1][a], Z2[a], X2[b], T, A);          // along y
+            double e = edge_log(X[a], Y[b], Z[0], Z[1], r[a][b][0], r[a][b][1], X2[a] + Y2[b], T);   // along z
+            e += edge_log(Y[a], Z[b], X[0], X[1], r[0][a][b], r[1][a][b], Y2[a] + Z2[b], T);          // along x
+            e += edge_log(Z[a], X[b], Y[0], Y[1], r[b][0][a], r[b][1][a], Z2[a] + X2[b], T);          // along y
             v += ((a + b) & 1) ? -e : e;
         }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        // the faces x = X[a] (corners (Y_j, Z_k)), y = Y[a] (corners (Z_k, X_i))
+        // and z = Z[a] (corners (X_i, Y_j))
+        const double rx[2][2] = {{r[a][0][0], r[a][0][1]}, {r[a][1][0], r[a][1][1]}};
+        const double ry[2][2] = {{r[0][a][0], r[1][a][0]}, {r[0][a][1], r[1][a][1]}};
+        const double rz[2][2] = {{r[0][0][a], r[0][1][a]}, {r[1][0][a], r[1][1][a]}};
+        const double dxv[2] = {dxy[a][0], dxy[a][1]}, dxw[2] = {dzx[0][a], dzx[1][a]};
+        const double dyv[2] = {dyz[a][0], dyz[a][1]}, dyw[2] = {dxy[0][a], dxy[1][a]};
+        const double dzv[2] = {dzx[a][0], dzx[a][1]}, dzw[2] = {dyz[0][a], dyz[1][a]};
+        const double tx = X[a] * fabs(X[a]) * face_half_angle(fabs(X[a]), rx, dxv, dxw, yz, A);
+        const double ty = Y[a] * fabs(Y[a]) * face_half_angle(fabs(Y[a]), ry, dyv, dyw, zx, A);
+        const double tz = Z[a] * fabs(Z[a]) * face_half_angle(fabs(Z[a]), rz, dzv, dzw, xy, A);
+        const double t = ((X[a] != 0.0) ? tx : 0.0) + ((Y[a] != 0.0) ? ty : 0.0) + ((Z[a] != 0.0) ? tz : 0.0);
+        v += a ? -t : t;
     }
     return v;
 }
