@@ -77,15 +77,15 @@ ALGO_BYTES_PER_WALK = 36
 # for a device copy of known size.  Figures are reported only while the
 # sources still hash to the recorded value.
 COUNTERS = {
-    "sources_sha256": "f62502d3529eca42fc0bf3261973b375b44d728d309a559619520bc0ece6f822",
-    "cfg4_mixed": {"valu_lane_instr_per_step": 108.16996, "valu_busy": 1.091188, "fp64_flop_per_step": 2.104391, "fp32_flop_per_step": 30.68011, "fetch_kib": 983853.125, "write_kib": 80741379.320312, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.99822},
-    "cfg4_f64": {"valu_lane_instr_per_step": 273.045701, "valu_busy": 0.9397, "fp64_flop_per_step": 143.527018, "fp32_flop_per_step": 0.06131, "fetch_kib": 803837.46875, "write_kib": 74560463.710938, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.998729},
-    "cfg2_f64": {"valu_lane_instr_per_step": 222.112173, "valu_busy": 0.977391, "fp64_flop_per_step": 108.152058, "fp32_flop_per_step": 0.073697, "fetch_kib": 173.09375, "write_kib": 875728.65625, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.874856},
-    "cfg2_mixed": {"valu_lane_instr_per_step": 84.679799, "valu_busy": 1.047813, "fp64_flop_per_step": 2.194113, "fp32_flop_per_step": 23.573059, "fetch_kib": 7843.53125, "write_kib": 1080410.085938, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.973796},
-    "cfg3_f64": {"valu_lane_instr_per_step": 268.136251, "valu_busy": 0.94474, "fp64_flop_per_step": 117.714184, "fp32_flop_per_step": 0.094087, "fetch_kib": 530427727.458333, "write_kib": 17314434.90625, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.86657},
-    "cfg3_mixed": {"valu_lane_instr_per_step": 112.046332, "valu_busy": 0.683603, "fp64_flop_per_step": 2.16552, "fp32_flop_per_step": 31.388704, "fetch_kib": 478212842.645833, "write_kib": 16338305.65625, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.87996},
-    "cfg3_f64_levels": {"valu_lane_instr_per_step": 266.624667, "valu_busy": 0.960222, "fp64_flop_per_step": 117.714334, "fp32_flop_per_step": 0.094088, "fetch_kib": 2825505.125, "write_kib": 29589589.822917, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.996256},
-    "cfg3_mixed_levels": {"valu_lane_instr_per_step": 111.011342, "valu_busy": 0.803178, "fp64_flop_per_step": 2.165514, "fp32_flop_per_step": 31.388701, "fetch_kib": 162974.0, "write_kib": 31368859.854167, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.99728},
+    "sources_sha256": "b81b8ba156f1b6bebea039cf29c012cacd50eb859f269059a5bb7748b3afd727",
+    "cfg4_mixed": {"valu_lane_instr_per_step": 103.1442, "valu_busy": 1.0912, "fp64_flop_per_step": 2.1044, "fp32_flop_per_step": 29.8313, "fetch_kib": 989844.125, "write_kib": 80809838.3125, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9982},
+    "cfg4_f64": {"valu_lane_instr_per_step": 266.572, "valu_busy": 0.9543, "fp64_flop_per_step": 143.5387, "fp32_flop_per_step": 0.0613, "fetch_kib": 803236.7656, "write_kib": 74477477.2578, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9987},
+    "cfg2_f64": {"valu_lane_instr_per_step": 220.0856, "valu_busy": 0.9664, "fp64_flop_per_step": 108.1519, "fp32_flop_per_step": 0.0736, "fetch_kib": 165.3438, "write_kib": 874613.9766, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8749},
+    "cfg2_mixed": {"valu_lane_instr_per_step": 84.5644, "valu_busy": 1.0447, "fp64_flop_per_step": 2.1943, "fp32_flop_per_step": 23.5735, "fetch_kib": 7840.4062, "write_kib": 1170381.8359, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.974},
+    "cfg3_f64": {"valu_lane_instr_per_step": 266.6016, "valu_busy": 0.9655, "fp64_flop_per_step": 117.7141, "fp32_flop_per_step": 0.0941, "fetch_kib": 470217398.1667, "write_kib": 17523813.375, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8798},
+    "cfg3_mixed": {"valu_lane_instr_per_step": 106.8117, "valu_busy": 0.6598, "fp64_flop_per_step": 2.1656, "fp32_flop_per_step": 30.5892, "fetch_kib": 480751933.0833, "write_kib": 16463584.375, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8766},
+    "cfg3_f64_levels": {"valu_lane_instr_per_step": 267.9558, "valu_busy": 0.9844, "fp64_flop_per_step": 117.7145, "fp32_flop_per_step": 0.0941, "fetch_kib": 135812.4792, "write_kib": 31285361.0625, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9977},
+    "cfg3_mixed_levels": {"valu_lane_instr_per_step": 111.1088, "valu_busy": 0.8128, "fp64_flop_per_step": 2.1655, "fp32_flop_per_step": 30.5883, "fetch_kib": 174694.7292, "write_kib": 31271300.6146, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9972},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp", "paper_1709_07469_amd/csrc/fk_stats.hpp",
