@@ -285,12 +285,24 @@ __device__ __forceinline__ void normals_f32(uint32_t wa, uint32_t wb, float& z0,
 // Density rho(x): voxel grid (zero outside), then analytic prisms [lo, hi),
 // then open balls; contributions add in that order.
 // ---------------------------------------------------------------------------
+// floor((x - o) / d), the quotient rounded as a division rounds it.  When d
+// is a power of two the reciprocal product is that quotient.  Otherwise the
+// product q with the rounded reciprocal inv lies within 3 ulp of it (one
+// rounding in inv, one in the product, one in the division), so floor(q) is
+// the quotient's floor unless q lies within 2^-50 |q| (8 ulp) of an
+// integer; only then, for about one coordinate in 10^14 away from grid
+// planes, the division runs.
 __device__ __forceinline__ double grid_axis_f64(double x, double o, double d, double inv, int exact)
 {
-    // floor((x - o) / d); when d is a power of two the reciprocal product is
-    // the same number as the quotient
-    const double q = exact ? (x - o) * inv : (x - o) / d;
-    return floor(q);
+    const double a = x - o;
+    const double q = a * inv;
+    double t = floor(q);
+    if (!exact) {
+        const double f = q - t;   // exact
+        const double e = fabs(q) * 0x1p-50;
+        if (__builtin_expect((f < e) | (f > 1.0 - e), 0)) t = floor(a / d);
+    }
+    return t;
 }
 
 // Voxel holding (x, y, z), or -1 outside the grid (or without a grid).

@@ -134,6 +134,28 @@ def test_f64_quadratic_data_and_constant_density(exit_rule):
     _check_f64_potential(pr)
 
 
+@pytest.mark.parametrize("precision", [W.PREC_F64, W.PREC_MIXED_F64ACC])
+def test_grid_indices_past_the_int_range(precision):
+    # A 3 x 2 x 2 grid of spacing 1e-10 at 0.5 beside a density-1.5 prism over
+    # the box: the walks' voxel coordinates reach -1.5e10 and +5e9, past the
+    # int range, where the conversions saturate and the lookup must read
+    # "outside".  The grid is never hit, so the solve equals the one without
+    # it bit for bit (and the FP64 walks match the oracle's).
+    base = W.Problem(stations=_ST4[:3], dt=1e-3, paths_per_station=1500, seed=4, G=0.7, bc_kind=W.BC_QUADRATIC,
+                     bc_data=_HARM, prisms=np.array([[-10, -10, -10, 10, 10, 10, 1.5]]), precision=precision,
+                     name="far-grid", **_BOX)
+    far = base.replace(rho=np.full((2, 2, 3), 4.0, dtype=np.float32), grid_origin=np.full(3, 0.5),
+                       grid_spacing=np.full(3, 1e-10))
+    say("case far grid prec", precision)
+    a, av, as_ = gpu_solve(base, 0)
+    b, bv, bs = gpu_solve(far, 0)
+    assert np.asarray(as_).tobytes() == np.asarray(bs).tobytes()
+    assert np.asarray(av).tobytes() == np.asarray(bv).tobytes()
+    assert np.asarray(a).tobytes() == np.asarray(b).tobytes()
+    if precision == W.PREC_F64:
+        _check_f64_potential(far)
+
+
 def _face_linear(box_lo, box_hi, face_n, lin):
     vals = []
     for f in range(6):
