@@ -710,27 +710,32 @@ __device__ __forceinline__ double edge_log(double u, double v, double wl, double
 }
 
 // The arctangent terms of one face of the prism, the plane u = U with corners
-// (v_j, w_k): half of sum_jk (-1)^(j+k) atan(v_j w_k / (|U| r_jk)), which is
-// the solid angle the face subtends from p, halved, for U > 0.  atan(q / p)
-// with p = |U| r > 0 and q = v w is twice the argument of
-// h = (|c| + p) + i q, |c| = sqrt(p^2 + q^2) = d_v d_w (the distances
-// sqrt(U^2 + v^2) and sqrt(U^2 + w^2) in the face's two coordinate planes),
-// and that argument lies in (-pi/4, pi/4).  The four arguments with their
-// signs add up to the argument of h00 conj(h01) conj(h10) h11, in (-pi, pi):
-// one atan2 per face.  au = |U|; vw[j][k] = v_j w_k.
-__device__ __forceinline__ double face_half_angle(double au, const double (&r)[2][2], const double (&dv)[2],
-                                                  const double (&dw)[2], const double (&vw)[2][2], const AtanTable& A)
+// (v_j, w_k): sum_jk (-1)^(j+k) atan(v_j w_k / (|U| r_jk)), the solid angle
+// the face subtends from p for U > 0.  Each term is the argument of
+// c_jk = |U| r_jk + i v_j w_k, inside (-pi/2, pi/2).  The two edge products
+// E0 = c00 conj(c01) and E1 = c11 conj(c10) have arguments inside (-pi, pi)
+// whose sum, inside (-2 pi, 2 pi), is the face's: the argument of E0 E1 (one
+// atan2), plus 2 pi when both edge arguments are positive and the product's
+// is negative, minus 2 pi in the mirrored case.  au = |U|; vw[j][k] = v_j w_k.
+__device__ __forceinline__ double face_angle(double au, const double (&r)[2][2], const double (&vw)[2][2],
+                                             const AtanTable& A)
 {
-    double re[2][2];
+    double p[2][2];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int k = 0; k < 2; ++k) re[j][k] = fma(au, r[j][k], dv[j] * dw[k]);
-    const double ar = fma(re[0][0], re[0][1], vw[0][0] * vw[0][1]);      // h00 conj(h01)
-    const double ai = fma(vw[0][0], re[0][1], -(re[0][0] * vw[0][1]));
-    const double br = fma(re[1][1], re[1][0], vw[1][1] * vw[1][0]);      // h11 conj(h10)
-    const double bi = fma(vw[1][1], re[1][0], -(re[1][1] * vw[1][0]));
-    return atan2_q(fma(ar, bi, ai * br), fma(ar, br, -(ai * bi)), A);
+        for (int k = 0; k < 2; ++k) p[j][k] = au * r[j][k];
+    const double e0r = fma(p[0][0], p[0][1], vw[0][0] * vw[0][1]);      // c00 conj(c01)
+    const double e0i = fma(vw[0][0], p[0][1], -(p[0][0] * vw[0][1]));
+    const double e1r = fma(p[1][1], p[1][0], vw[1][1] * vw[1][0]);      // c11 conj(c10)
+    const double e1i = fma(vw[1][1], p[1][0], -(p[1][1] * vw[1][0]));
+    const double pr = fma(e0r, e1r, -(e0i * e1i));
+    const double pi = fma(e0r, e1i, e0i * e1r);
+    const double two_pi = 0x1.921fb54442d18p+2;
+    const double wrap = ((e0i > 0.0) & (e1i > 0.0) & (pi < 0.0))   ? two_pi
+                        : ((e0i < 0.0) & (e1i < 0.0) & (pi > 0.0)) ? -two_pi
+                                                                   : 0.0;
+    return atan2_q(pi, pr, A) + wrap;
 }
 
 // Newtonian integral of the unit-density prism [lo, hi] seen from p: the
@@ -741,15 +746,15 @@ __device__ __forceinline__ double face_half_angle(double au, const double (&r)[2
 // number of upper coordinates (Nagy, Papp & Benedek 2000); a term whose
 // prefactor is zero vanishes.  The logarithms are taken in pairs along each
 // of the 12 edges (edge_log) and the arctangents by face: the face U = U_a
-// contributes (-1)^a U_a |U_a| times its half angle (face_half_angle).  That
-// is 8 corner distances and 12 in-plane ones (sqrt_nonneg, from the hardware
-// reciprocal square root: a distance is zero or far above the subnormal
-// range), 12 logarithms and 6 arctangents instead of 24 of each, with no
-// cancellation between the two corners' large logarithms.  Every term is
-// evaluated and the vanishing ones selected away (their logarithm or
-// quotient may be infinite), so the lanes of a wavefront -- whose exit
-// points differ -- take no branches.  The face products are of degree 8 in
-// the coordinates: exact for |coordinates| up to about 1e37.
+// contributes (-1)^a U_a |U_a| / 2 times its angle (face_angle).  That is 8
+// corner distances (sqrt_nonneg, from the hardware reciprocal square root:
+// a distance is zero or far above the subnormal range), 12 logarithms and 6
+// arctangents instead of 24 of each, with no cancellation between the two
+// corners' large logarithms.  Every term is evaluated and the vanishing ones
+// selected away (their logarithm or quotient may be infinite), so the lanes
+// of a wavefront -- whose exit points differ -- take no branches.  The face
+// products are of degree 8 in the coordinates: exact for |coordinates| up
+// to about 1e37.
 __device__ inline double prism_newton(const double* q, double px, double py, double pz, const DataTables& tb)
 {
     const BmTables& T = *tb.bm;
@@ -760,16 +765,12 @@ __device__ inline double prism_newton(const double* q, double px, double py, dou
     const double X2[2] = {X[0] * X[0], X[1] * X[1]};
     const double Y2[2] = {Y[0] * Y[0], Y[1] * Y[1]};
     const double Z2[2] = {Z[0] * Z[0], Z[1] * Z[1]};
-    double r[2][2][2];   // r[i][j][k] at corner (X[i], Y[j], Z[k])
-    double dxy[2][2], dyz[2][2], dzx[2][2];   // dxy[i][j] = |(X[i], Y[j])|, dyz[j][k], dzx[k][i]
-    double xy[2][2], yz[2][2], zx[2][2];      // xy[i][j] = X[i] Y[j], ...
+    double r[2][2][2];                    // r[i][j][k] at corner (X[i], Y[j], Z[k])
+    double xy[2][2], yz[2][2], zx[2][2];  // xy[i][j] = X[i] Y[j], ...
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            dxy[i][j] = sqrt_nonneg(X2[i] + Y2[j]);
-            dyz[i][j] = sqrt_nonneg(Y2[i] + Z2[j]);
-            dzx[i][j] = sqrt_nonneg(Z2[i] + X2[j]);
             xy[i][j] = X[i] * Y[j];
             yz[i][j] = Y[i] * Z[j];
             zx[i][j] = Z[i] * X[j];
@@ -795,14 +796,11 @@ __device__ inline double prism_newton(const double* q, double px, double py, dou
         const double rx[2][2] = {{r[a][0][0], r[a][0][1]}, {r[a][1][0], r[a][1][1]}};
         const double ry[2][2] = {{r[0][a][0], r[1][a][0]}, {r[0][a][1], r[1][a][1]}};
         const double rz[2][2] = {{r[0][0][a], r[0][1][a]}, {r[1][0][a], r[1][1][a]}};
-        const double dxv[2] = {dxy[a][0], dxy[a][1]}, dxw[2] = {dzx[0][a], dzx[1][a]};
-        const double dyv[2] = {dyz[a][0], dyz[a][1]}, dyw[2] = {dxy[0][a], dxy[1][a]};
-        const double dzv[2] = {dzx[a][0], dzx[a][1]}, dzw[2] = {dyz[0][a], dyz[1][a]};
-        const double tx = X[a] * fabs(X[a]) * face_half_angle(fabs(X[a]), rx, dxv, dxw, yz, A);
-        const double ty = Y[a] * fabs(Y[a]) * face_half_angle(fabs(Y[a]), ry, dyv, dyw, zx, A);
-        const double tz = Z[a] * fabs(Z[a]) * face_half_angle(fabs(Z[a]), rz, dzv, dzw, xy, A);
+        const double tx = X[a] * fabs(X[a]) * face_angle(fabs(X[a]), rx, yz, A);
+        const double ty = Y[a] * fabs(Y[a]) * face_angle(fabs(Y[a]), ry, zx, A);
+        const double tz = Z[a] * fabs(Z[a]) * face_angle(fabs(Z[a]), rz, xy, A);
         const double t = ((X[a] != 0.0) ? tx : 0.0) + ((Y[a] != 0.0) ? ty : 0.0) + ((Z[a] != 0.0) ? tz : 0.0);
-        v += a ? -t : t;
+        v += a ? -0.5 * t : 0.5 * t;
     }
     return v;
 }
