@@ -77,15 +77,15 @@ ALGO_BYTES_PER_WALK = 36
 # for a device copy of known size.  Figures are reported only while the
 # sources still hash to the recorded value.
 COUNTERS = {
-    "sources_sha256": "b81b8ba156f1b6bebea039cf29c012cacd50eb859f269059a5bb7748b3afd727",
-    "cfg4_mixed": {"valu_lane_instr_per_step": 103.1442, "valu_busy": 1.0912, "fp64_flop_per_step": 2.1044, "fp32_flop_per_step": 29.8313, "fetch_kib": 989844.125, "write_kib": 80809838.3125, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9982},
-    "cfg4_f64": {"valu_lane_instr_per_step": 266.572, "valu_busy": 0.9543, "fp64_flop_per_step": 143.5387, "fp32_flop_per_step": 0.0613, "fetch_kib": 803236.7656, "write_kib": 74477477.2578, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9987},
-    "cfg2_f64": {"valu_lane_instr_per_step": 220.0856, "valu_busy": 0.9664, "fp64_flop_per_step": 108.1519, "fp32_flop_per_step": 0.0736, "fetch_kib": 165.3438, "write_kib": 874613.9766, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8749},
-    "cfg2_mixed": {"valu_lane_instr_per_step": 84.5644, "valu_busy": 1.0447, "fp64_flop_per_step": 2.1943, "fp32_flop_per_step": 23.5735, "fetch_kib": 7840.4062, "write_kib": 1170381.8359, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.974},
-    "cfg3_f64": {"valu_lane_instr_per_step": 266.6016, "valu_busy": 0.9655, "fp64_flop_per_step": 117.7141, "fp32_flop_per_step": 0.0941, "fetch_kib": 470217398.1667, "write_kib": 17523813.375, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8798},
-    "cfg3_mixed": {"valu_lane_instr_per_step": 106.8117, "valu_busy": 0.6598, "fp64_flop_per_step": 2.1656, "fp32_flop_per_step": 30.5892, "fetch_kib": 480751933.0833, "write_kib": 16463584.375, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8766},
-    "cfg3_f64_levels": {"valu_lane_instr_per_step": 267.9558, "valu_busy": 0.9844, "fp64_flop_per_step": 117.7145, "fp32_flop_per_step": 0.0941, "fetch_kib": 135812.4792, "write_kib": 31285361.0625, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9977},
-    "cfg3_mixed_levels": {"valu_lane_instr_per_step": 111.1088, "valu_busy": 0.8128, "fp64_flop_per_step": 2.1655, "fp32_flop_per_step": 30.5883, "fetch_kib": 174694.7292, "write_kib": 31271300.6146, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9972},
+    "sources_sha256": "13a8f96675fa2293e6b5f4727a0471f5a828ba5ff3f58bbb8faefe9a51a53933",
+    "cfg4_mixed": {"valu_lane_instr_per_step": 103.1445, "valu_busy": 1.0914, "fp64_flop_per_step": 2.1044, "fp32_flop_per_step": 29.8315, "fetch_kib": 990478.625, "write_kib": 80833520.9375, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9982},
+    "cfg4_f64": {"valu_lane_instr_per_step": 257.1338, "valu_busy": 0.9469, "fp64_flop_per_step": 120.4111, "fp32_flop_per_step": 0.0613, "fetch_kib": 801893.3281, "write_kib": 74730830.7344, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9987},
+    "cfg2_f64": {"valu_lane_instr_per_step": 220.0988, "valu_busy": 0.9733, "fp64_flop_per_step": 108.1516, "fp32_flop_per_step": 0.0735, "fetch_kib": 159.6875, "write_kib": 874643.4141, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8749},
+    "cfg2_mixed": {"valu_lane_instr_per_step": 84.5649, "valu_busy": 1.0378, "fp64_flop_per_step": 2.1937, "fp32_flop_per_step": 23.5718, "fetch_kib": 7844.875, "write_kib": 1167325.8594, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.974},
+    "cfg3_f64": {"valu_lane_instr_per_step": 263.2246, "valu_busy": 0.9741, "fp64_flop_per_step": 117.7144, "fp32_flop_per_step": 0.0941, "fetch_kib": 470155050.7708, "write_kib": 17541594.8438, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8799},
+    "cfg3_mixed": {"valu_lane_instr_per_step": 106.812, "valu_busy": 0.6606, "fp64_flop_per_step": 2.1655, "fp32_flop_per_step": 30.589, "fetch_kib": 480752704.7708, "write_kib": 16468303.4583, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8767},
+    "cfg3_f64_levels": {"valu_lane_instr_per_step": 266.0853, "valu_busy": 0.9891, "fp64_flop_per_step": 117.7144, "fp32_flop_per_step": 0.0941, "fetch_kib": 136226.9583, "write_kib": 31309027.9583, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9977},
+    "cfg3_mixed_levels": {"valu_lane_instr_per_step": 111.1093, "valu_busy": 0.8134, "fp64_flop_per_step": 2.1655, "fp32_flop_per_step": 30.5884, "fetch_kib": 174639.8333, "write_kib": 31272458.3542, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9972},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp", "paper_1709_07469_amd/csrc/fk_stats.hpp",
