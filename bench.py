@@ -77,15 +77,15 @@ ALGO_BYTES_PER_WALK = 36
 # for a device copy of known size.  Figures are reported only while the
 # sources still hash to the recorded value.
 COUNTERS = {
-    "sources_sha256": "3eac7cbde1641c3dca404adfb803e77ab34c10a2a08648473014967965551b0c",
-    "cfg4_mixed": {"valu_lane_instr_per_step": 103.1445, "valu_busy": 1.0914, "fp64_flop_per_step": 2.1044, "fp32_flop_per_step": 29.8315, "fetch_kib": 990478.625, "write_kib": 80833520.9375, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9982},
-    "cfg4_f64": {"valu_lane_instr_per_step": 257.1338, "valu_busy": 0.9469, "fp64_flop_per_step": 120.4111, "fp32_flop_per_step": 0.0613, "fetch_kib": 801893.3281, "write_kib": 74730830.7344, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9987},
-    "cfg2_f64": {"valu_lane_instr_per_step": 220.0988, "valu_busy": 0.9733, "fp64_flop_per_step": 108.1516, "fp32_flop_per_step": 0.0735, "fetch_kib": 159.6875, "write_kib": 874643.4141, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8749},
-    "cfg2_mixed": {"valu_lane_instr_per_step": 84.5649, "valu_busy": 1.0378, "fp64_flop_per_step": 2.1937, "fp32_flop_per_step": 23.5718, "fetch_kib": 7844.875, "write_kib": 1167325.8594, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.974},
-    "cfg3_f64": {"valu_lane_instr_per_step": 263.2246, "valu_busy": 0.9741, "fp64_flop_per_step": 117.7144, "fp32_flop_per_step": 0.0941, "fetch_kib": 470155050.7708, "write_kib": 17541594.8438, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8799},
-    "cfg3_mixed": {"valu_lane_instr_per_step": 106.812, "valu_busy": 0.6606, "fp64_flop_per_step": 2.1655, "fp32_flop_per_step": 30.589, "fetch_kib": 480752704.7708, "write_kib": 16468303.4583, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.8767},
-    "cfg3_f64_levels": {"valu_lane_instr_per_step": 266.0853, "valu_busy": 0.9891, "fp64_flop_per_step": 117.7144, "fp32_flop_per_step": 0.0941, "fetch_kib": 136226.9583, "write_kib": 31309027.9583, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9977},
-    "cfg3_mixed_levels": {"valu_lane_instr_per_step": 111.1093, "valu_busy": 0.8134, "fp64_flop_per_step": 2.1655, "fp32_flop_per_step": 30.5884, "fetch_kib": 174639.8333, "write_kib": 31272458.3542, "fetch_scale": 1.999922, "write_scale": 1.0, "l2_hit": 0.9972},
+    "sources_sha256": "c32df42d9cb8d2a74286ff80e714ef25820a8e3b38ced9b5f946827f59d3a723",
+    "cfg4_mixed": {"valu_lane_instr_per_step": 103.1444, "valu_busy": 1.0913, "fp64_flop_per_step": 2.1044, "fp32_flop_per_step": 29.8313, "fetch_kib": 989051.3594, "write_kib": 80812283.2188, "fetch_scale": 1.999921, "write_scale": 1.0, "l2_hit": 0.9982},
+    "cfg4_f64": {"valu_lane_instr_per_step": 257.1337, "valu_busy": 0.9469, "fp64_flop_per_step": 120.411, "fp32_flop_per_step": 0.0613, "fetch_kib": 799770.3594, "write_kib": 74725090.4297, "fetch_scale": 1.999921, "write_scale": 1.0, "l2_hit": 0.9987},
+    "cfg2_f64": {"valu_lane_instr_per_step": 214.8479, "valu_busy": 0.967, "fp64_flop_per_step": 108.1473, "fp32_flop_per_step": 0.073, "fetch_kib": 168.7188, "write_kib": 879037.625, "fetch_scale": 1.999921, "write_scale": 1.0, "l2_hit": 0.8743},
+    "cfg2_mixed": {"valu_lane_instr_per_step": 84.5602, "valu_busy": 1.0337, "fp64_flop_per_step": 2.1943, "fp32_flop_per_step": 23.5735, "fetch_kib": 7842.6875, "write_kib": 1169483.7031, "fetch_scale": 1.999921, "write_scale": 1.0, "l2_hit": 0.974},
+    "cfg3_f64": {"valu_lane_instr_per_step": 263.2239, "valu_busy": 0.9743, "fp64_flop_per_step": 117.7145, "fp32_flop_per_step": 0.0941, "fetch_kib": 470147505.9792, "write_kib": 17541360.9792, "fetch_scale": 1.999921, "write_scale": 1.0, "l2_hit": 0.8799},
+    "cfg3_mixed": {"valu_lane_instr_per_step": 106.8119, "valu_busy": 0.6596, "fp64_flop_per_step": 2.1656, "fp32_flop_per_step": 30.5892, "fetch_kib": 480741901.4792, "write_kib": 16468283.5312, "fetch_scale": 1.999921, "write_scale": 1.0, "l2_hit": 0.8767},
+    "cfg3_f64_levels": {"valu_lane_instr_per_step": 266.0865, "valu_busy": 0.9891, "fp64_flop_per_step": 117.7144, "fp32_flop_per_step": 0.0941, "fetch_kib": 135953.8958, "write_kib": 31307932.0104, "fetch_scale": 1.999921, "write_scale": 1.0, "l2_hit": 0.9977},
+    "cfg3_mixed_levels": {"valu_lane_instr_per_step": 111.1091, "valu_busy": 0.8127, "fp64_flop_per_step": 2.1655, "fp32_flop_per_step": 30.5884, "fetch_kib": 174965.0833, "write_kib": 31272405.9792, "fetch_scale": 1.999921, "write_scale": 1.0, "l2_hit": 0.9972},
 }
 TRAFFIC_SOURCES = ("paper_1709_07469_amd/csrc/fk_walk.hip", "paper_1709_07469_amd/csrc/fk_device.hpp",
                    "paper_1709_07469_amd/csrc/fk_internal.hpp", "paper_1709_07469_amd/csrc/fk_stats.hpp",

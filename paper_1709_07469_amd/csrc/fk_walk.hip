@@ -1316,11 +1316,13 @@ const void* walk_fn(int precision, bool dense)
                                        : (const void*)walk_kernel<false, false, ADJ, LOOP>;
 }
 
-// FP64 batches keep the per-lane key: their walks already fill the scalar
-// registers (the shared source's bodies, the FP64 bounds), and with the key
-// schedule there too they spill more and measured 9 % slower (grid batch).
+// FP64 batches take the uniform key only with one shared source (+2 % on
+// the SI-prism FP64 batch).  Batches of separate sources keep the per-lane
+// key: their walks already fill the scalar registers, and with the key
+// schedule there too they spill more and measured 1.6 % slower (the
+// 32-model FP64 grid batch).
 template <bool SHARED, bool UKEY>
-constexpr bool kF64Ukey = false;
+constexpr bool kF64Ukey = SHARED && UKEY;
 
 template <int LOOP, bool SHARED, bool UKEY>
 const void* batch_fn(int precision)

@@ -49,6 +49,21 @@ def test_batch_equals_standalone_bitwise(precision, seeds):
         assert np.array_equal(bv.view(np.uint64), av.view(np.uint64)) and np.array_equal(bs, as_)
 
 
+@pytest.mark.parametrize("precision", [W.PREC_F64, W.PREC_MIXED_F64ACC, W.PREC_MIXED_KAHAN])
+def test_shared_source_batch_equals_standalone_bitwise(precision):
+    """u and g_z of one SI-prism model in one batch: the two problems share
+    the source and the seed, so every precision runs the kernel that holds
+    the source and the generator key in scalar registers."""
+    from paper_1709_07469_amd import fkgrav as F
+    pr = W.cfg2(60, precision=precision)
+    pr = pr.replace(stations=pr.stations[::5])
+    say("shared-source batch precision", precision)
+    res, ws, PB, _ = F.solve_batch([pr, pr], [0, 1])
+    for m, k in enumerate((0, 1)):
+        alone, _, _ = F.solve(pr, k)
+        assert res[m].tobytes() == alone.tobytes(), (precision, m)
+
+
 @pytest.mark.parametrize("walks", [(2, 3), (2, 5, 4), (7, 2, 3, 9)])
 def test_tiny_batches_of_separate_sources_equal_standalone(walks):
     """Batches of problems with their own sources split the queue into
