@@ -126,6 +126,28 @@ _BOX = dict(box_lo=np.array([-1.0, -1.0, -1.0]), box_hi=np.array([1.0, 1.0, 1.0]
 _ST4 = np.array([[0.0, 0.0, 0.0], [0.5, -0.3, 0.2], [-0.7, 0.6, -0.4], [0.1, 0.85, 0.7]])
 
 
+def test_f64_stations_on_grid_planes():
+    # Stations placed on voxel planes of a grid whose spacings are not powers
+    # of two: every walk's start density needs the floor of a quotient that
+    # lies within a few ulp of an integer (for the station at o + d along x,
+    # rounded, just below 1), where the kernels' reciprocal product gives way
+    # to the division.  Walk by walk against the oracle.
+    rng = np.random.default_rng(8)
+    n = np.array([8, 8, 8])
+    d = np.array([0.1, 0.13, 0.07])
+    o = -0.5 * n * d
+    rho = rng.choice(np.array([0.3, 0.8, 1.4, 2.2], dtype=np.float32), size=n[::-1])
+    ks = [(3, 5, 2), (4, 4, 4), (1, 6, 7), (5, 2, 3)]
+    st = np.array([[o[c] + k[c] * d[c] for c in range(3)] for k in ks])
+    q = (st - o) * (1.0 / d)
+    f = q - np.floor(q)
+    e = np.abs(q) * 2.0 ** -50
+    assert np.all((f < e) | (f > 1.0 - e))          # every start coordinate takes the division
+    pr = W.Problem(stations=st, dt=1e-3, paths_per_station=300, seed=12, G=0.9, rho=rho, grid_origin=o,
+                   grid_spacing=d, name="grid-planes", **_BOX)
+    _check_f64_potential(pr)
+
+
 @pytest.mark.parametrize("exit_rule", [W.EXIT_OVERSHOOT, W.EXIT_INTERSECT])
 def test_f64_quadratic_data_and_constant_density(exit_rule):
     pr = W.Problem(stations=_ST4, dt=1e-2, paths_per_station=1500, seed=9, G=0.7, bc_kind=W.BC_QUADRATIC,
